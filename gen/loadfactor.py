@@ -1,0 +1,130 @@
+"""Certified minimum-congestion bracket used to scale demands to a load factor.
+
+For an instance with capacities u and demands d, the minimum congestion
+mu* = min over all routings of max_e (flow_e / u_e) is the reciprocal of the
+maximum concurrent flow. Scaling d by alpha = LF / mu* gives load factor LF:
+the scaled instance is feasible iff LF <= 1 (Section 1's constraint system).
+
+mu* is bracketed by path column generation on the path LP
+
+    min mu  s.t.  sum_{p in P_k} x_p = d_k,  sum_{p ∋ e} x_p <= mu u_e,  x >= 0,
+
+solved with HiGHS. mu_hi is the value of the restricted master (an explicit
+routing), mu_lo = sum_k d_k dist_l(s_k, t_k) / sum_e u_e l_e for the master's
+dual arc lengths l (weak duality), so mu_lo <= mu* <= mu_hi. Demands scaled by
+LF / mu_hi are certified feasible for LF <= 1.
+
+This is instance generation, not part of the PDR method.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+from scipy.optimize import linprog
+from scipy.sparse import csc_matrix, csr_matrix
+from scipy.sparse.csgraph import dijkstra
+
+
+def _shortest_paths(n, tails, heads, lengths, s, t, chunk=512):
+    """Shortest s_k -> t_k paths under positive arc lengths.
+
+    Returns (dist[K], list of arc-id arrays).
+    """
+    m = len(heads)
+    A = csr_matrix((lengths, (tails, heads)), shape=(n, n))
+    keys = tails.astype(np.int64) * n + heads.astype(np.int64)
+    order = np.argsort(keys, kind="stable")
+    skeys = keys[order]
+    K = len(s)
+    dist = np.empty(K)
+    paths = [None] * K
+    srcs, inv = np.unique(s, return_inverse=True)
+    for c0 in range(0, len(srcs), chunk):
+        block = srcs[c0:c0 + chunk]
+        D, P = dijkstra(A, directed=True, indices=block, return_predecessors=True)
+        ks = np.nonzero((inv >= c0) & (inv < c0 + len(block)))[0]
+        rows = inv[ks] - c0
+        dist[ks] = D[rows, t[ks]]
+        cur = t[ks].astype(np.int64)
+        src = s[ks].astype(np.int64)
+        arcs_rev = [[] for _ in range(len(ks))]
+        active = np.nonzero(cur != src)[0]
+        while active.size:
+            prev = P[rows[active], cur[active]].astype(np.int64)
+            if np.any(prev < 0):
+                raise RuntimeError("unreachable commodity sink")
+            pos = np.searchsorted(skeys, prev * n + cur[active])
+            arc = order[pos]
+            for a_i, arc_id in zip(active.tolist(), arc.tolist()):
+                arcs_rev[a_i].append(arc_id)
+            cur[active] = prev
+            active = active[cur[active] != src[active]]
+        for j, k in enumerate(ks.tolist()):
+            paths[k] = np.array(arcs_rev[j][::-1], dtype=np.int64)
+    assert m == len(tails)
+    return dist, paths
+
+
+def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: bool = False,
+                       time_limit: float = 7200.0):
+    """Return dict(mu_hi, mu_lo, iters, columns) for the instance's demands."""
+    n, m, K = inst.n, inst.m, inst.K
+    tails = inst.tails().astype(np.int64)
+    heads = inst.col.astype(np.int64)
+    u = inst.u.astype(np.float64)
+    d = inst.d.astype(np.float64)
+    s = inst.s.astype(np.int64)
+    t = inst.t.astype(np.int64)
+    t0 = time.time()
+
+    # initial columns: fewest-hop paths
+    _, paths = _shortest_paths(n, tails, heads, np.ones(m), s, t)
+    col_k = list(range(K))
+    col_arcs = list(paths)
+    seen = set((k, tuple(p.tolist())) for k, p in enumerate(paths))
+
+    mu_lo = 0.0
+    mu_hi = np.inf
+    it = 0
+    for it in range(1, max_iter + 1):
+        P = len(col_arcs)
+        lens = np.array([len(a) for a in col_arcs], dtype=np.int64)
+        rows = np.concatenate(col_arcs)
+        cols = np.repeat(np.arange(1, P + 1), lens)
+        A_ub = csc_matrix((np.concatenate([-u, np.ones(len(rows))]),
+                           (np.concatenate([np.arange(m), rows]),
+                            np.concatenate([np.zeros(m, dtype=np.int64), cols]))),
+                          shape=(m, P + 1))
+        A_eq = csc_matrix((np.ones(P), (np.array(col_k), np.arange(1, P + 1))), shape=(K, P + 1))
+        c = np.zeros(P + 1)
+        c[0] = 1.0
+        res = linprog(c, A_ub=A_ub, b_ub=np.zeros(m), A_eq=A_eq, b_eq=d,
+                      bounds=(0, None), method="highs")
+        if res.status != 0:
+            raise RuntimeError(f"master LP failed: {res.message}")
+        mu_hi = min(mu_hi, float(res.fun))
+        lam = np.maximum(0.0, -np.asarray(res.ineqlin.marginals))
+        pi = np.asarray(res.eqlin.marginals)
+        # strictly positive lengths keep Dijkstra well defined; the bound is valid for any l >= 0
+        lp = lam + 1e-9 * max(lam.max(), 1e-300) + 1e-300
+        dist, newp = _shortest_paths(n, tails, heads, lp, s, t)
+        mu_lo = max(mu_lo, float(np.dot(d, dist) / np.dot(u, lp)))
+        if verbose:
+            print(f"[cg] it {it} cols {P} mu_hi {mu_hi:.6g} mu_lo {mu_lo:.6g} "
+                  f"gap {mu_hi / mu_lo - 1:.2e} t {time.time() - t0:.1f}s", flush=True)
+        if mu_hi <= mu_lo * (1.0 + gap) or time.time() - t0 > time_limit:
+            break
+        added = 0
+        for k in np.nonzero(dist < pi - 1e-12 * np.maximum(1.0, np.abs(pi)))[0].tolist():
+            key = (k, tuple(newp[k].tolist()))
+            if key in seen:
+                continue
+            seen.add(key)
+            col_k.append(k)
+            col_arcs.append(newp[k])
+            added += 1
+        if added == 0:
+            break
+    return dict(mu_hi=mu_hi, mu_lo=mu_lo, iters=it, columns=len(col_arcs),
+                seconds=time.time() - t0)
