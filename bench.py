@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of one PDR sweep on one MI355X.
+
+A step is one pass of the hot path over the whole instance: the excess ->
+height reduction, the objective and stop test, and the arc update of every
+(arc, commodity) pair. The workload is the 100 x 100 bidirectional grid
+(n 10,000, m 39,600) with K = 10,000 commodities, demands scaled to load
+factor 0.95 (synthetic, seeded; shaped like the paper's grid benchmark family).
+
+Prints ONE JSON line. `value` is edge x commodity updates per second of PDR-ESO
+in FP64 with all data resident in HBM. `roofline` prices the arc-update kernel
+(the dominant kernel) against the MI355X HBM peak; `cpu_baseline` times the
+FP64 CPU oracle on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "PDR edge×commodity updates/s + time-to-residual 1e-8, FP32+polish vs FP64"
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2108_07549_amd", "csrc", "pdr_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(key: str):
+    """Per-launch HBM bytes from the committed rocprofv3 counter summary, if it
+    was taken from the current kernel source; else None."""
+    try:
+        with open(COUNTERS) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = tab.get(key)
+    if not entry or entry.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def time_variant(pdr, torch, inst, method, precision, steps, warmup):
+    """Warm up, then time exactly `steps` sweeps; returns timing and per-kernel ms."""
+    ctx = pdr.Context.from_instance(inst, method=method, precision=precision)
+    try:
+        ctx.sweep(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = ctx.profile_sweeps(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = ctx.residual()
+        tiling = ctx.tiling()
+    finally:
+        ctx.destroy()
+    sec = t1 - t0
+    return dict(seconds=sec, ms_per_step=1e3 * sec / steps,
+                updates_per_s=inst.m * inst.K * steps / sec,
+                kernel_ms_avg=dict(height=kms[0] / steps, objective=kms[1] / steps,
+                                   arc=kms[2] / steps),
+                z_after=res["z"], tiling=dict(lanes_per_arc=tiling[0], vec_per_lane=tiling[1],
+                                              Kp=tiling[2]))
+
+
+def cpu_baseline(inst, sweeps):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.run(inst, oracle.ESO, sweeps)
+    sec = time.perf_counter() - t0
+    return dict(value=inst.m * inst.K * sweeps / sec, unit="updates/s",
+                cores=oracle.num_threads(), kind="oracle",
+                sample=f"{sweeps} PDR-ESO FP64 sweeps of the full workload from f = 0 "
+                       f"({sec:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="grid100_k10000")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design, not a build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_07549_amd as pdr
+    from gen.instance import load_instance
+
+    inst = load_instance(args.workload)
+    print(f"[bench] {args.workload}: n {inst.n} m {inst.m} K {inst.K}; "
+          f"{args.warmup} warmup + {args.steps} timed sweeps", file=sys.stderr, flush=True)
+    head = time_variant(pdr, torch, inst, pdr.ESO, pdr.FP64, args.steps, args.warmup)
+    print(f"[bench] eso fp64: {head['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
+
+    n, m, K = inst.n, inst.m, inst.K
+    w = 8
+    arc_bytes = w * (2 * m * K + n * K)  # read f, write f, read each h row once
+    arc_ms = head["kernel_ms_avg"]["arc"]
+    achieved = arc_bytes / (arc_ms * 1e-3) / 1e9
+    traffic = measured_traffic(f"k_eso_fp64:{args.workload}")
+    sweep_bytes = w * (3 * m * K + 2 * n * K)
+    out = {
+        "metric": METRIC,
+        "value": head["updates_per_s"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "K": K, "method": "eso",
+                   "precision": "fp64", "load_factor": inst.meta.get("load_factor"),
+                   "lf_bracket": inst.meta.get("lf_bracket"), "tiling": head["tiling"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_eso<double>", "algorithmic_bytes_per_launch": arc_bytes,
+                     "avg_launch_ms": arc_ms},
+        "sweep_roofline": {"algorithmic_bytes": sweep_bytes,
+                           "achieved_GBs": sweep_bytes / (head["ms_per_step"] * 1e-3) / 1e9,
+                           "frac": sweep_bytes / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernel_ms_avg": head["kernel_ms_avg"],
+    }
+    if not args.no_variants:
+        var = {}
+        for name, meth, prec in (("agd_fp64", pdr.AGD, pdr.FP64), ("eso_fp32", pdr.ESO, pdr.FP32_BULK),
+                                 ("agd_fp32", pdr.AGD, pdr.FP32_BULK)):
+            r = time_variant(pdr, torch, inst, meth, prec, args.steps, args.warmup)
+            print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
+            var[name] = dict(updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"],
+                             kernel_ms_avg=r["kernel_ms_avg"], tiling=r["tiling"])
+        out["variants"] = var
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: {args.cpu_sweeps} oracle sweeps", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -10,7 +10,7 @@ Load-factor scaling multiplies integer demands by ``alpha = LF / mu_hi``, where
 ``mu_hi`` is the congestion of an explicit routing of the unscaled demands
 (see ``gen.loadfactor``). The factors for the large recipes are stored in
 ``gen/loadfactor.json`` by ``gen/certify.py`` so that no LP runs at benchmark
-time; ``load_instance`` recomputes them when the file has no entry.
+time; ``load_instance`` raises ``MissingLoadFactor`` when the file has no entry.
 """
 from __future__ import annotations
 
@@ -156,6 +156,10 @@ def _lf_table() -> dict:
     return {}
 
 
+class MissingLoadFactor(KeyError):
+    pass
+
+
 def load_instance(name: str, seed: Optional[int] = None, scale: bool = True) -> Instance:
     """Build a named recipe and apply its load-factor scaling (if it has one)."""
     fn = RECIPES[name]
@@ -166,9 +170,7 @@ def load_instance(name: str, seed: Optional[int] = None, scale: bool = True) -> 
     key = f"{name}:{inst.meta['seed']}"
     entry = _lf_table().get(key)
     if entry is None:
-        from .loadfactor import congestion_bracket
-        br = congestion_bracket(inst)
-        entry = dict(mu_hi=br["mu_hi"], mu_lo=br["mu_lo"])
+        raise MissingLoadFactor(f"{key} has no entry in {_LF_FILE}; run python -m gen.certify {name}")
     alpha = lf / entry["mu_hi"]
     out = inst.demand_scaled(alpha)
     out.meta.update(mu_hi=entry["mu_hi"], mu_lo=entry["mu_lo"],

@@ -67,8 +67,17 @@ def _shortest_paths(n, tails, heads, lengths, s, t, chunk=512):
 
 
 def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: bool = False,
-                       time_limit: float = 7200.0):
-    """Return dict(mu_hi, mu_lo, iters, columns) for the instance's demands."""
+                       time_limit: float = 7200.0, kappa: float = 12.0):
+    """Return dict(mu_hi, mu_lo, iters, columns) for the instance's demands.
+
+    Columns come from two pricing rules per iteration: shortest paths under the
+    master's dual arc lengths (classical column generation) and shortest paths
+    under exponential congestion lengths exp(kappa * (load_e / u_e / mu - 1)) / u_e
+    of the master's routing (the multiplicative-weights rule), which spreads
+    flow over many bottlenecks at once. Both length vectors also give a weak
+    duality lower bound; the larger is kept. Columns unused for three
+    consecutive masters are dropped.
+    """
     n, m, K = inst.n, inst.m, inst.K
     tails = inst.tails().astype(np.int64)
     heads = inst.col.astype(np.int64)
@@ -82,7 +91,21 @@ def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: boo
     _, paths = _shortest_paths(n, tails, heads, np.ones(m), s, t)
     col_k = list(range(K))
     col_arcs = list(paths)
+    idle = [0] * K
     seen = set((k, tuple(p.tolist())) for k, p in enumerate(paths))
+
+    def add_columns(newp, ks):
+        added = 0
+        for k in ks:
+            key = (k, tuple(newp[k].tolist()))
+            if key in seen:
+                continue
+            seen.add(key)
+            col_k.append(k)
+            col_arcs.append(newp[k])
+            idle.append(0)
+            added += 1
+        return added
 
     mu_lo = 0.0
     mu_hi = np.inf
@@ -104,26 +127,37 @@ def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: boo
         if res.status != 0:
             raise RuntimeError(f"master LP failed: {res.message}")
         mu_hi = min(mu_hi, float(res.fun))
+        x = np.asarray(res.x[1:])
+        load = np.bincount(rows, weights=np.repeat(x, lens), minlength=m)
         lam = np.maximum(0.0, -np.asarray(res.ineqlin.marginals))
         pi = np.asarray(res.eqlin.marginals)
         # strictly positive lengths keep Dijkstra well defined; the bound is valid for any l >= 0
         lp = lam + 1e-9 * max(lam.max(), 1e-300) + 1e-300
         dist, newp = _shortest_paths(n, tails, heads, lp, s, t)
         mu_lo = max(mu_lo, float(np.dot(d, dist) / np.dot(u, lp)))
+        rho = load / u / max(float(res.fun), 1e-300)
+        lx = np.exp(kappa * (rho - 1.0)) / u
+        dist_x, newp_x = _shortest_paths(n, tails, heads, lx, s, t)
+        mu_lo = max(mu_lo, float(np.dot(d, dist_x) / np.dot(u, lx)))
         if verbose:
             print(f"[cg] it {it} cols {P} mu_hi {mu_hi:.6g} mu_lo {mu_lo:.6g} "
                   f"gap {mu_hi / mu_lo - 1:.2e} t {time.time() - t0:.1f}s", flush=True)
         if mu_hi <= mu_lo * (1.0 + gap) or time.time() - t0 > time_limit:
             break
-        added = 0
-        for k in np.nonzero(dist < pi - 1e-12 * np.maximum(1.0, np.abs(pi)))[0].tolist():
-            key = (k, tuple(newp[k].tolist()))
-            if key in seen:
-                continue
-            seen.add(key)
-            col_k.append(k)
-            col_arcs.append(newp[k])
-            added += 1
+        # drop columns idle for three masters
+        keep = []
+        for q in range(P):
+            idle[q] = 0 if x[q] > 0 else idle[q] + 1
+            if idle[q] < 3:
+                keep.append(q)
+        if len(keep) < P:
+            col_k[:] = [col_k[q] for q in keep]
+            col_arcs[:] = [col_arcs[q] for q in keep]
+            idle[:] = [idle[q] for q in keep]
+            seen.clear()
+            seen.update((k, tuple(a.tolist())) for k, a in zip(col_k, col_arcs))
+        added = add_columns(newp, np.nonzero(dist < pi - 1e-12 * np.maximum(1.0, np.abs(pi)))[0].tolist())
+        added += add_columns(newp_x, range(K))
         if added == 0:
             break
     return dict(mu_hi=mu_hi, mu_lo=mu_lo, iters=it, columns=len(col_arcs),

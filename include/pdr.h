@@ -1,0 +1,182 @@
+/*
+ * pdr.h -- C ABI of the MI355X (gfx950) Potential Difference Reduction library.
+ *
+ * The library runs the PDR method for multicommodity-flow feasibility
+ * (Liu, "A Localized Method for Multicommodity Flow Problem", arXiv 2108.07549):
+ * a pseudo-flow f >= 0 is improved by sweeps. Each sweep computes the excess
+ * Delta and the vertex heights h (Section 3.1, Expressions 2-4), the arc
+ * congestion psi (Expression 5) and the objective z (Algorithm 1), applies the
+ * stop test of Algorithm 1 on the device, and then updates every arc in
+ * parallel, either by the exact edge subproblem (PDR-ESO: Expression 14,
+ * Algorithm 2) or by the adaptive-gradient step (PDR-AGD: Algorithm 3).
+ *
+ * Conventions for every call:
+ *  - No C++ exception crosses the ABI. Every call returns a pdr_status; the
+ *    text of the last failure is returned by pdr_last_error.
+ *  - Host arrays passed in are read during the call only and stay owned by
+ *    the caller. Output host arrays are owned by the caller.
+ *  - The context owns all device memory it allocates. A context is not
+ *    thread-safe; distinct contexts are independent.
+ *  - Work runs on the context's HIP stream (the caller's stream from
+ *    pdr_options.stream, or one the library creates at default priority).
+ *  - After a device error the context is poisoned: every later call returns
+ *    PDR_ERR_DEVICE until pdr_destroy.
+ *  - Flows are exchanged as m x K row-major arrays (arc-major, commodity
+ *    contiguous) in the caller's CSR arc order.
+ */
+#ifndef PDR_H
+#define PDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdr_ctx pdr_ctx;
+
+typedef enum {
+    PDR_OK = 0,
+    PDR_ERR_INVALID = 1, /* bad argument or instance; nothing was changed */
+    PDR_ERR_OOM = 2,     /* device memory would not fit; nothing was allocated */
+    PDR_ERR_DEVICE = 3,  /* a HIP call failed; the context is poisoned */
+    PDR_ERR_STATE = 4,   /* call not valid in the context's current state */
+    PDR_ERR_NUMERIC = 5  /* the objective became non-finite */
+} pdr_status;
+
+typedef enum { PDR_ESO = 0, PDR_AGD = 1 } pdr_method;
+
+/* PDR_FP64: f and h stored and updated in FP64.
+ * PDR_FP32_BULK: f and h stored and updated in FP32; excess accumulation,
+ * per-arc sums, the objective and the stop test stay in FP64. */
+typedef enum { PDR_FP64 = 0, PDR_FP32_BULK = 1 } pdr_precision;
+
+typedef enum { PDR_UNDECIDED = 0, PDR_FEASIBLE = 1, PDR_INFEASIBLE = 2 } pdr_verdict;
+
+/* Parameters of Algorithm 3. Defaults are the paper's experimental settings
+ * (Section 7.2): beta_init 0.25, beta_min 1/K, beta_max 0.5, alpha_inc 2,
+ * alpha_dec 0.5; the increase period is 10 iterations (Algorithm 3).
+ * beta_min <= 0 means 1/K. */
+typedef struct {
+    double beta_init, beta_min, beta_max, alpha_inc, alpha_dec;
+    int32_t inc_period;
+} pdr_agd_params;
+
+typedef struct {
+    int32_t method;        /* pdr_method */
+    int32_t precision;     /* pdr_precision */
+    pdr_agd_params agd;
+    double z_feasible_tol; /* verdict FEASIBLE needs z <= this (default 1e-8) */
+    void *stream;          /* hipStream_t to run on, or NULL */
+    int32_t lanes_per_arc; /* 0: automatic; else a power of two 1..1024 (tuning) */
+    int32_t vec_per_lane;  /* 0: automatic; else 1, 2, 4 or 8 (tuning) */
+} pdr_options;
+
+/* FP64 residual report of the current flows (see pdr_residual). */
+typedef struct {
+    double z;              /* objective of Algorithm 1 / Expression 8 */
+    double z_psi;          /* 1/2 sum_e psi_e^2 */
+    double z_h;            /* 1/2 sum_{i,k} delta_i h_ik^2 */
+    double kkt_sq;         /* sum rho^2, rho = phi if f > 0 else max(0, phi) (Section 3.3) */
+    double max_abs_excess; /* max |Delta_ik| */
+    double max_congestion; /* max psi_e */
+    double farkas_gap;     /* sum_k d_k (h_sk - h_tk) - sum_e u_e max(0, max_k (h_ik - h_jk)) */
+    double farkas_tol;     /* rounding margin of farkas_gap */
+    int64_t sweeps_done;   /* arc updates applied since init (iteration counter t) */
+    int64_t evaluations;   /* objective evaluations recorded in the z log */
+    int32_t verdict;       /* pdr_verdict: INFEASIBLE if farkas_gap > farkas_tol,
+                              else FEASIBLE if z <= z_feasible_tol, else UNDECIDED */
+    int32_t stopped;       /* 1 if the last pdr_sweep call ended on its stop test */
+} pdr_residual_t;
+
+/* Fill *opt with the defaults (ESO, FP64, the paper's AGD parameters,
+ * z_feasible_tol 1e-8, stream NULL, automatic tiling). */
+void pdr_default_options(pdr_options *opt);
+
+/*
+ * Create a context for one instance (Section 1): a directed graph G(V, E)
+ * with n vertices given as an out-adjacency CSR (row_ptr[n+1], int64,
+ * row_ptr[0] = 0, non-decreasing, row_ptr[n] = m; col[m] = head of each arc,
+ * arc e has tail i with row_ptr[i] <= e < row_ptr[i+1]), capacities u[m],
+ * and K commodities (s[K], t[K], d[K]) with s_k != t_k.
+ * Flows start at 0 and, for AGD, learning rates at beta_init (Algorithms 1, 3).
+ * Host arrays are deep-copied; opt may be NULL for the defaults.
+ * Errors: PDR_ERR_INVALID for n < 1, m < 0, K < 1, a malformed CSR, a head
+ * out of range, a self-loop, u or d negative or non-finite, s or t out of
+ * range, s_k == t_k, or a commodity endpoint of degree 0; PDR_ERR_OOM if the
+ * device buffers would not fit; PDR_ERR_DEVICE for a HIP failure. On failure
+ * *out is set to NULL.
+ */
+pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
+                    const int32_t *col, const double *u, int32_t K, const int32_t *s,
+                    const int32_t *t, const double *d, const pdr_options *opt);
+
+/*
+ * Enqueue up to max_sweeps passes of Algorithm 1 (ESO) or Algorithm 3 (AGD).
+ * Each pass computes h, psi and z from the current flows, records z in the z
+ * log, stops if eps_obj > 0 and |z - z_prev| < eps_obj (z_prev = +inf before
+ * the first pass since init) or if z_target > 0 and z <= z_target, and
+ * otherwise updates every arc (Jacobi: all arcs read the same h).
+ * The stop test runs on the device. With no stop test active the call only
+ * enqueues work; otherwise it polls the device between batches of passes.
+ * Errors: PDR_ERR_INVALID for max_sweeps < 0; PDR_ERR_DEVICE.
+ */
+pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_target);
+
+/* Compute the FP64 residual report of the current flows (synchronizes).
+ * Returns PDR_ERR_NUMERIC (and fills *out) if z is not finite. */
+pdr_status pdr_residual(pdr_ctx *ctx, pdr_residual_t *out);
+
+/* Copy the current flows as FP64 into host_out[m*K] (synchronizes). */
+pdr_status pdr_flows(pdr_ctx *ctx, double *host_out);
+
+/* Write the current flows into caller-owned device memory dev_out[m*K] on
+ * the context stream, as FP64 if fp64 != 0 else FP32 (no host sync). */
+pdr_status pdr_flows_device(pdr_ctx *ctx, void *dev_out, int32_t fp64);
+
+/* Copy the FP64 heights h[n*K] of the current flows (Expression 4) to the
+ * host (synchronizes). */
+pdr_status pdr_heights(pdr_ctx *ctx, double *host_out);
+
+/* Copy the AGD learning rates beta[m] to the host (synchronizes). */
+pdr_status pdr_learning_rates(pdr_ctx *ctx, double *host_out);
+
+/* Copy z log entries [first, first + count) to host_out (synchronizes).
+ * Entry q is the objective of the q-th evaluation since init. The log keeps
+ * the last 2^20 evaluations; older entries return PDR_ERR_INVALID. */
+pdr_status pdr_z_log(pdr_ctx *ctx, int64_t first, int64_t count, double *host_out);
+
+/* Switch the storage precision. FP32_BULK -> FP64 widens the current flows
+ * exactly (the FP64 "polish" phase); FP64 -> FP32_BULK rounds them. The
+ * iteration counter, z_prev and learning rates are kept. */
+pdr_status pdr_set_precision(pdr_ctx *ctx, int32_t precision);
+
+/* Replace the run state: flows f[m*K] (FP64, >= 0, finite), AGD rates
+ * beta[m] (may be NULL to keep), iteration counter t and z_prev
+ * (+inf to restart the stop test). Used to resume a saved run. */
+pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, int64_t t,
+                         double z_prev);
+
+/* Measurement: run `sweeps` passes like pdr_sweep without a stop test,
+ * recording HIP events around every kernel on the context stream. On return
+ * (synchronized) kernel_ms[0], [1], [2] hold the summed device time in
+ * milliseconds of the height, objective and arc-update kernels. */
+pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
+
+/* Query the automatic tiling: lanes per arc and vectors per lane of the arc
+ * kernels, and the padded commodity stride Kp. */
+pdr_status pdr_tiling(const pdr_ctx *ctx, int32_t *lanes_per_arc, int32_t *vec_per_lane,
+                      int32_t *Kp);
+
+/* Release the context and all its device memory. NULL is ignored. */
+void pdr_destroy(pdr_ctx *ctx);
+
+/* Text of the last failure of ctx, or of the calling thread's last failed
+ * pdr_init when ctx is NULL. Never NULL. */
+const char *pdr_last_error(const pdr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDR_H */

@@ -1,0 +1,239 @@
+"""MI355X-native Potential Difference Reduction (PDR) sweep for multicommodity-flow feasibility.
+
+Thin ctypes binding over ``libpdr.so`` (the C ABI of ``include/pdr.h``). Every
+step of a sweep runs in the library's HIP kernels; this module only marshals
+arguments. It raises if the library is missing -- there is no CPU fallback.
+
+Method: Liu, "A Localized Method for Multicommodity Flow Problem" (arXiv 2108.07549):
+heights from excess (Section 3.1), the exact edge subproblem (PDR-ESO,
+Section 4, Algorithms 1-2) and the adaptive-gradient update (PDR-AGD,
+Section 5.1, Algorithm 3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdr.so")
+
+ESO, AGD = 0, 1
+FP64, FP32_BULK = 0, 1
+VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
+STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVICE",
+          4: "PDR_ERR_STATE", 5: "PDR_ERR_NUMERIC"}
+
+EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_residual", "pdr_flows",
+           "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_z_log",
+           "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_tiling", "pdr_destroy",
+           "pdr_last_error"]
+
+
+class PdrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class AgdParams(C.Structure):
+    _fields_ = [("beta_init", C.c_double), ("beta_min", C.c_double), ("beta_max", C.c_double),
+                ("alpha_inc", C.c_double), ("alpha_dec", C.c_double), ("inc_period", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("agd", AgdParams),
+                ("z_feasible_tol", C.c_double), ("stream", C.c_void_p),
+                ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32)]
+
+
+class Residual(C.Structure):
+    _fields_ = [("z", C.c_double), ("z_psi", C.c_double), ("z_h", C.c_double),
+                ("kkt_sq", C.c_double), ("max_abs_excess", C.c_double),
+                ("max_congestion", C.c_double), ("farkas_gap", C.c_double),
+                ("farkas_tol", C.c_double), ("sweeps_done", C.c_int64),
+                ("evaluations", C.c_int64), ("verdict", C.c_int32), ("stopped", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["verdict"] = VERDICT[int(self.verdict)]
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libpdr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2108_07549_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.pdr_default_options.argtypes = [C.POINTER(Options)]
+        L.pdr_default_options.restype = None
+        L.pdr_init.argtypes = [C.POINTER(P), i32, i32, P, P, P, i32, P, P, P, C.POINTER(Options)]
+        L.pdr_sweep.argtypes = [P, i64, dbl, dbl]
+        L.pdr_residual.argtypes = [P, C.POINTER(Residual)]
+        L.pdr_flows.argtypes = [P, P]
+        L.pdr_flows_device.argtypes = [P, P, i32]
+        L.pdr_heights.argtypes = [P, P]
+        L.pdr_learning_rates.argtypes = [P, P]
+        L.pdr_z_log.argtypes = [P, i64, i64, P]
+        L.pdr_set_precision.argtypes = [P, i32]
+        L.pdr_set_state.argtypes = [P, P, P, i64, dbl]
+        L.pdr_profile_sweeps.argtypes = [P, i64, P]
+        L.pdr_tiling.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.pdr_destroy.argtypes = [P]
+        L.pdr_destroy.restype = None
+        L.pdr_last_error.argtypes = [P]
+        L.pdr_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("pdr_default_options", "pdr_destroy", "pdr_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream: the HIP stream on ROCm
+
+
+def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, vec_per_lane=0,
+                    z_feasible_tol=1e-8, agd=None) -> Options:
+    opt = Options()
+    lib().pdr_default_options(C.byref(opt))
+    opt.method = int(method)
+    opt.precision = int(precision)
+    opt.stream = _stream_handle(stream)
+    opt.lanes_per_arc = int(lanes_per_arc)
+    opt.vec_per_lane = int(vec_per_lane)
+    opt.z_feasible_tol = float(z_feasible_tol)
+    if agd:
+        for k, v in agd.items():
+            setattr(opt.agd, k, v)
+    return opt
+
+
+class Context:
+    """One PDR instance resident on the GPU (wraps pdr_init ... pdr_destroy)."""
+
+    def __init__(self, n, row_ptr, col, u, s, t, d, method=ESO, precision=FP64, stream=None,
+                 lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None):
+        L = lib()
+        self._h = C.c_void_p()
+        self._keep = [np.ascontiguousarray(row_ptr, np.int64), np.ascontiguousarray(col, np.int32),
+                      np.ascontiguousarray(u, np.float64), np.ascontiguousarray(s, np.int32),
+                      np.ascontiguousarray(t, np.int32), np.ascontiguousarray(d, np.float64)]
+        rp, cl, uu, ss, tt, dd = self._keep
+        self.n, self.m, self.K = int(n), int(cl.shape[0]), int(ss.shape[0])
+        opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane,
+                              z_feasible_tol, agd)
+        st = L.pdr_init(C.byref(self._h), int(n), self.m, _ptr(rp), _ptr(cl), _ptr(uu), self.K,
+                        _ptr(ss), _ptr(tt), _ptr(dd), C.byref(opt))
+        if st != 0:
+            raise PdrError(st, L.pdr_last_error(None).decode())
+        self._keep = None
+
+    @classmethod
+    def from_instance(cls, inst, **kw) -> "Context":
+        return cls(inst.n, inst.row_ptr, inst.col, inst.u, inst.s, inst.t, inst.d, **kw)
+
+    # -- helpers
+    def _check(self, st):
+        if st != 0:
+            raise PdrError(st, lib().pdr_last_error(self._h).decode())
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- ABI mirror
+    def sweep(self, max_sweeps: int, eps_obj: float = 0.0, z_target: float = 0.0):
+        self._check(lib().pdr_sweep(self._h, int(max_sweeps), float(eps_obj), float(z_target)))
+
+    def residual(self) -> dict:
+        r = Residual()
+        st = lib().pdr_residual(self._h, C.byref(r))
+        if st not in (0, 5):
+            self._check(st)
+        out = r.as_dict()
+        out["status"] = STATUS[st]
+        return out
+
+    def flows(self) -> np.ndarray:
+        out = np.empty((self.m, self.K), np.float64)
+        self._check(lib().pdr_flows(self._h, _ptr(out)))
+        return out
+
+    def flows_device(self, out_tensor, fp64: bool = True):
+        """Write flows into a caller-owned device tensor of m*K elements."""
+        self._check(lib().pdr_flows_device(self._h, C.c_void_p(out_tensor.data_ptr()),
+                                           1 if fp64 else 0))
+        return out_tensor
+
+    def heights(self) -> np.ndarray:
+        out = np.empty((self.n, self.K), np.float64)
+        self._check(lib().pdr_heights(self._h, _ptr(out)))
+        return out
+
+    def learning_rates(self) -> np.ndarray:
+        out = np.empty(self.m, np.float64)
+        self._check(lib().pdr_learning_rates(self._h, _ptr(out)))
+        return out
+
+    def z_log(self, first: int, count: int) -> np.ndarray:
+        out = np.empty(max(int(count), 1), np.float64)
+        self._check(lib().pdr_z_log(self._h, int(first), int(count), _ptr(out)))
+        return out[:count]
+
+    def set_precision(self, precision: int):
+        self._check(lib().pdr_set_precision(self._h, int(precision)))
+
+    def set_state(self, f, beta=None, t: int = 0, z_prev: float = float("inf")):
+        fa = np.ascontiguousarray(f, np.float64)
+        ba = None if beta is None else np.ascontiguousarray(beta, np.float64)
+        self._check(lib().pdr_set_state(self._h, _ptr(fa), None if ba is None else _ptr(ba),
+                                        int(t), float(z_prev)))
+
+    def profile_sweeps(self, sweeps: int) -> np.ndarray:
+        """Run sweeps without a stop test; returns summed device ms of the
+        (height, objective, arc) kernels measured with HIP events."""
+        out = np.zeros(3, np.float64)
+        self._check(lib().pdr_profile_sweeps(self._h, int(sweeps), _ptr(out)))
+        return out
+
+    def tiling(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().pdr_tiling(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def destroy(self):
+        if self._h:
+            lib().pdr_destroy(self._h)
+            self._h = C.c_void_p()
+
+    close = destroy
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,772 @@
+// Host side of the C ABI declared in include/pdr.h: argument validation,
+// device memory, the stream, and the launch sequence of a sweep.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "pdr.h"
+#include "pdr_internal.h"
+
+using pdr::Ctrl;
+using pdr::DevGraph;
+using pdr::Tiling;
+
+namespace {
+thread_local std::string g_init_error;
+constexpr int kMaxLanes = 1024;
+constexpr int kMaxNv = 8;
+}  // namespace
+
+struct pdr_ctx {
+    int32_t n = 0, m = 0, K = 0, Kp = 0;
+    int32_t method = PDR_ESO;
+    int32_t precision = PDR_FP64;
+    pdr_agd_params agd{};
+    double beta_min = 0.0;
+    double z_feasible_tol = 1e-8;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t req_lanes = 0, req_nv = 0;
+    Tiling tiling{1, 1};
+    bool poisoned = false;
+    std::string err;
+
+    DevGraph g{};
+    // instance arrays (device)
+    int32_t *d_row_ptr = nullptr, *d_tails = nullptr, *d_heads = nullptr, *d_in_ptr = nullptr,
+            *d_in_idx = nullptr, *d_deg = nullptr, *d_inj_ptr = nullptr, *d_inj_k = nullptr,
+            *d_s = nullptr, *d_t = nullptr;
+    double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
+    // run state (device)
+    double *f64 = nullptr, *h64 = nullptr;
+    float *f32 = nullptr, *h32 = nullptr;
+    double *Fsum = nullptr, *beta = nullptr, *zpart = nullptr, *maxpart = nullptr,
+           *arcpart = nullptr, *resout = nullptr, *zlog = nullptr;
+    int64_t nzpart = 0;
+    Ctrl *ctrl = nullptr;
+    // pinned host mirrors
+    Ctrl *h_ctrl = nullptr;
+    double *h_res = nullptr;
+    std::vector<void *> allocs;
+};
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+pdr_status fail(pdr_ctx *c, pdr_status st, const std::string &msg)
+{
+    c->err = msg;
+    return st;
+}
+
+pdr_status dev_fail(pdr_ctx *c, hipError_t e, const char *what)
+{
+    c->poisoned = true;
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return PDR_ERR_DEVICE;
+}
+
+#define PDR_CHECK(ctx, expr)                                          \
+    do {                                                              \
+        hipError_t _e = (expr);                                       \
+        if (_e != hipSuccess) return dev_fail((ctx), _e, #expr);      \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(pdr_ctx *c, T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e == hipSuccess) {
+        c->allocs.push_back(q);
+        *p = static_cast<T *>(q);
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t upload(pdr_ctx *c, T **p, const T *src, size_t count)
+{
+    hipError_t e = dalloc(c, p, count);
+    if (e != hipSuccess) return e;
+    if (count) e = hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
+int pow2ceil(int64_t x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int vec_of(int32_t precision) { return precision == PDR_FP64 ? 2 : 4; }
+
+Tiling auto_tiling(int32_t Kp, int32_t precision)
+{
+    const int64_t nvec = Kp / vec_of(precision);
+    int L = pow2ceil((nvec + 3) / 4);
+    if (L > kMaxLanes) L = kMaxLanes;
+    int nv = pow2ceil((nvec + L - 1) / L);
+    if (nv < 1) nv = 1;
+    return Tiling{L, nv};
+}
+
+bool tiling_covers(Tiling tl, int32_t Kp, int32_t precision)
+{
+    const int64_t nvec = Kp / vec_of(precision);
+    return pdr::tiling_supported(tl.lanes, tl.nv) && (int64_t)tl.lanes * tl.nv >= nvec;
+}
+
+pdr_status choose_tiling(pdr_ctx *c, int32_t precision, Tiling *out)
+{
+    Tiling tl = auto_tiling(c->Kp, precision);
+    if (c->req_lanes > 0 || c->req_nv > 0) {
+        tl.lanes = c->req_lanes > 0 ? c->req_lanes : tl.lanes;
+        tl.nv = c->req_nv > 0 ? c->req_nv : pow2ceil((c->Kp / vec_of(precision) + tl.lanes - 1) /
+                                                    tl.lanes);
+    }
+    if (!tiling_covers(tl, c->Kp, precision)) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "no supported arc tiling covers K=%d (padded %d) in this precision "
+                 "(lanes %d x vectors %d; at most %d x %d vectors of 16 bytes per arc)",
+                 c->K, c->Kp, tl.lanes, tl.nv, kMaxLanes, kMaxNv);
+        c->err = buf;
+        return PDR_ERR_INVALID;
+    }
+    *out = tl;
+    return PDR_OK;
+}
+
+bool usable(pdr_ctx *c, pdr_status *st)
+{
+    if (!c) {
+        *st = PDR_ERR_INVALID;
+        return false;
+    }
+    if (c->poisoned) {
+        *st = PDR_ERR_DEVICE;
+        return false;
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) {
+        *st = dev_fail(c, e, "hipSetDevice");
+        return false;
+    }
+    return true;
+}
+
+void *cur_f(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->f64 : (void *)c->f32; }
+void *cur_h(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->h64 : (void *)c->h32; }
+
+pdr_status ensure_buffers(pdr_ctx *c, int32_t precision)
+{
+    const size_t mK = (size_t)c->m * c->Kp, nK = (size_t)c->n * c->Kp;
+    if (precision == PDR_FP64) {
+        if (!c->f64) {
+            hipError_t e = dalloc(c, &c->f64, mK);
+            if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (f)");
+            PDR_CHECK(c, e);
+        }
+    } else {
+        if (!c->f32) {
+            hipError_t e = dalloc(c, &c->f32, mK);
+            if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (f)");
+            PDR_CHECK(c, e);
+        }
+        if (!c->h32) {
+            hipError_t e = dalloc(c, &c->h32, nK);
+            if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (h)");
+            PDR_CHECK(c, e);
+        }
+    }
+    if (!c->h64) {  // FP64 heights: the FP64 sweep's h and every residual report
+        hipError_t e = dalloc(c, &c->h64, nK);
+        if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (h)");
+        PDR_CHECK(c, e);
+    }
+    return PDR_OK;
+}
+
+pdr_status sync_ctrl(pdr_ctx *c)
+{
+    PDR_CHECK(c, hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+pdr_status push_ctrl(pdr_ctx *c)
+{
+    PDR_CHECK(c, hipMemcpyAsync(c->ctrl, c->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+void free_all(pdr_ctx *c)
+{
+    // teardown: failures here cannot be reported and leave nothing to undo
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    if (c->h_res) (void)hipHostFree(c->h_res);
+    c->h_ctrl = nullptr;
+    c->h_res = nullptr;
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+void pdr_default_options(pdr_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->method = PDR_ESO;
+    opt->precision = PDR_FP64;
+    opt->agd.beta_init = 0.25;
+    opt->agd.beta_min = 0.0;  // 1/K
+    opt->agd.beta_max = 0.5;
+    opt->agd.alpha_inc = 2.0;
+    opt->agd.alpha_dec = 0.5;
+    opt->agd.inc_period = 10;
+    opt->z_feasible_tol = 1e-8;
+    opt->stream = nullptr;
+    opt->lanes_per_arc = 0;
+    opt->vec_per_lane = 0;
+}
+
+const char *pdr_last_error(const pdr_ctx *ctx)
+{
+    if (!ctx) return g_init_error.c_str();
+    return ctx->err.c_str();
+}
+
+static pdr_status init_fail(pdr_ctx *c, pdr_status st, pdr_ctx **out)
+{
+    g_init_error = c->err;
+    free_all(c);
+    delete c;
+    *out = nullptr;
+    return st;
+}
+
+pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
+                    const int32_t *col, const double *u, int32_t K, const int32_t *s,
+                    const int32_t *t, const double *d, const pdr_options *opt_in)
+{
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PDR_ERR_INVALID;
+    }
+    *out = nullptr;
+    pdr_options opt;
+    pdr_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    auto invalid = [&](const std::string &msg) {
+        g_init_error = msg;
+        return PDR_ERR_INVALID;
+    };
+    // ---- instance validation (Section 1: G(V, E), u: E -> Q+, (s_k, t_k, d_k), s_k != t_k)
+    if (n < 1) return invalid("n must be >= 1");
+    if (m < 0) return invalid("m must be >= 0");
+    if (K < 1) return invalid("K must be >= 1");
+    if (!row_ptr || (m > 0 && (!col || !u)) || !s || !t || !d)
+        return invalid("a required array is NULL");
+    if (row_ptr[0] != 0) return invalid("row_ptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return invalid("row_ptr must be non-decreasing");
+    if (row_ptr[n] != (int64_t)m) return invalid("row_ptr[n] must equal m");
+    std::vector<int32_t> deg(n, 0), tails(m);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n) return invalid("arc head out of range");
+            if (col[e] == i) return invalid("self-loop arcs are not allowed");
+            tails[e] = i;
+            deg[i] += 1;
+            deg[col[e]] += 1;
+        }
+    for (int32_t e = 0; e < m; ++e)
+        if (!finite_nonneg(u[e])) return invalid("capacities must be finite and >= 0");
+    for (int32_t k = 0; k < K; ++k) {
+        if (s[k] < 0 || s[k] >= n || t[k] < 0 || t[k] >= n)
+            return invalid("commodity endpoint out of range");
+        if (s[k] == t[k]) return invalid("commodity with s_k == t_k");
+        if (!finite_nonneg(d[k])) return invalid("demands must be finite and >= 0");
+        if (deg[s[k]] == 0 || deg[t[k]] == 0)
+            return invalid("commodity endpoint has degree 0 (its height is undefined)");
+    }
+    // ---- options
+    if (opt.method != PDR_ESO && opt.method != PDR_AGD) return invalid("unknown method");
+    if (opt.precision != PDR_FP64 && opt.precision != PDR_FP32_BULK)
+        return invalid("unknown precision");
+    if (opt.method == PDR_AGD) {
+        const pdr_agd_params &a = opt.agd;
+        if (!(a.beta_init > 0) || !(a.beta_max > 0) || !(a.alpha_inc > 0) || !(a.alpha_dec > 0) ||
+            !std::isfinite(a.beta_init) || !std::isfinite(a.beta_max) ||
+            !std::isfinite(a.alpha_inc) || !std::isfinite(a.alpha_dec) ||
+            !std::isfinite(a.beta_min) || a.inc_period < 0)
+            return invalid("invalid AGD parameters");
+    }
+    if (!(opt.z_feasible_tol >= 0) || !std::isfinite(opt.z_feasible_tol))
+        return invalid("z_feasible_tol must be finite and >= 0");
+    if (opt.lanes_per_arc < 0 || opt.vec_per_lane < 0) return invalid("negative tiling request");
+
+    pdr_ctx *c = new pdr_ctx();
+    c->n = n;
+    c->m = m;
+    c->K = K;
+    c->Kp = (int32_t)(K <= 64 ? (K + 3) / 4 * 4 : (K + 31) / 32 * 32);
+    c->method = opt.method;
+    c->precision = opt.precision;
+    c->agd = opt.agd;
+    c->beta_min = opt.agd.beta_min > 0 ? opt.agd.beta_min : 1.0 / K;
+    c->z_feasible_tol = opt.z_feasible_tol;
+    c->req_lanes = opt.lanes_per_arc;
+    c->req_nv = opt.vec_per_lane;
+    {
+        pdr_status st = choose_tiling(c, c->precision, &c->tiling);
+        if (st != PDR_OK) return init_fail(c, st, out);
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        c->err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return init_fail(c, PDR_ERR_DEVICE, out);
+    }
+    if (opt.stream) {
+        c->stream = (hipStream_t)opt.stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            c->err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            return init_fail(c, PDR_ERR_DEVICE, out);
+        }
+        c->own_stream = true;
+    }
+
+    // ---- memory estimate before any allocation
+    {
+        const double w = c->precision == PDR_FP64 ? 8.0 : 4.0;
+        const double mK = (double)m * c->Kp, nK = (double)n * c->Kp;
+        double need = mK * w + nK * w + nK * 8.0 * (c->precision == PDR_FP64 ? 0.0 : 1.0) +
+                      8.0 * (6.0 * m + 4.0 * n + 4.0 * K) + 8.0 * (double)pdr::kZLogCap +
+                      16.0 * (double)pdr::height_blocks(DevGraph{n, m, K, c->Kp}, 8);
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) {
+            c->err = std::string("hipMemGetInfo: ") + hipGetErrorString(e);
+            return init_fail(c, PDR_ERR_DEVICE, out);
+        }
+        if (need > 0.98 * (double)free_b) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "instance needs %.3g GB of device memory, %.3g GB free",
+                     need / 1e9, (double)free_b / 1e9);
+            c->err = buf;
+            return init_fail(c, PDR_ERR_OOM, out);
+        }
+    }
+
+    // ---- host-side graph preparation: CSC of in-arcs, degrees, injections
+    std::vector<int32_t> rp32(n + 1), in_ptr(n + 1, 0), in_idx(m), inj_ptr(n + 1, 0),
+        inj_k(2 * (size_t)K);
+    std::vector<double> inj_val(2 * (size_t)K);
+    for (int32_t i = 0; i <= n; ++i) rp32[i] = (int32_t)row_ptr[i];
+    for (int32_t q = 0; q < m; ++q) in_ptr[col[q] + 1] += 1;
+    for (int32_t i = 0; i < n; ++i) in_ptr[i + 1] += in_ptr[i];
+    {
+        std::vector<int32_t> fill(in_ptr.begin(), in_ptr.end() - 1);
+        for (int32_t q = 0; q < m; ++q) in_idx[fill[col[q]]++] = q;  // ascending arc id per head
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        inj_ptr[s[k] + 1] += 1;
+        inj_ptr[t[k] + 1] += 1;
+    }
+    for (int32_t i = 0; i < n; ++i) inj_ptr[i + 1] += inj_ptr[i];
+    {
+        std::vector<int32_t> fill(inj_ptr.begin(), inj_ptr.end() - 1);
+        for (int32_t k = 0; k < K; ++k) {
+            inj_k[fill[s[k]]] = k;
+            inj_val[fill[s[k]]++] = d[k];
+            inj_k[fill[t[k]]] = k;
+            inj_val[fill[t[k]]++] = -d[k];
+        }
+    }
+
+    auto oom_or_dev = [&](hipError_t err, const char *what) {
+        if (err == hipErrorOutOfMemory) {
+            c->err = std::string("out of device memory: ") + what;
+            return init_fail(c, PDR_ERR_OOM, out);
+        }
+        c->err = std::string(what) + ": " + hipGetErrorString(err);
+        return init_fail(c, PDR_ERR_DEVICE, out);
+    };
+#define PDR_UP(ptr, src, cnt)                                  \
+    do {                                                       \
+        hipError_t _e = upload(c, &(ptr), (src), (size_t)(cnt)); \
+        if (_e != hipSuccess) return oom_or_dev(_e, #ptr);     \
+    } while (0)
+    PDR_UP(c->d_row_ptr, rp32.data(), n + 1);
+    PDR_UP(c->d_tails, tails.data(), m);
+    PDR_UP(c->d_heads, col, m);
+    PDR_UP(c->d_in_ptr, in_ptr.data(), n + 1);
+    PDR_UP(c->d_in_idx, in_idx.data(), m);
+    PDR_UP(c->d_deg, deg.data(), n);
+    PDR_UP(c->d_inj_ptr, inj_ptr.data(), n + 1);
+    PDR_UP(c->d_inj_k, inj_k.data(), 2 * (size_t)K);
+    PDR_UP(c->d_inj_val, inj_val.data(), 2 * (size_t)K);
+    PDR_UP(c->d_u, u, m);
+    PDR_UP(c->d_s, s, K);
+    PDR_UP(c->d_t, t, K);
+    PDR_UP(c->d_d, d, K);
+#undef PDR_UP
+    c->g = DevGraph{n,         m,          K,           c->Kp,         c->d_row_ptr, c->d_tails,
+                    c->d_heads, c->d_in_ptr, c->d_in_idx, c->d_deg,     c->d_inj_ptr, c->d_inj_k,
+                    c->d_inj_val, c->d_u,   c->d_s,      c->d_t,        c->d_d};
+
+    pdr_status st = ensure_buffers(c, c->precision);
+    if (st != PDR_OK) return init_fail(c, st, out);
+    c->nzpart = pdr::height_blocks(c->g, 8);  // FP64 needs the most blocks
+#define PDR_AL(ptr, cnt)                                     \
+    do {                                                     \
+        hipError_t _e = dalloc(c, &(ptr), (size_t)(cnt));    \
+        if (_e != hipSuccess) return oom_or_dev(_e, #ptr);   \
+    } while (0)
+    PDR_AL(c->Fsum, m);
+    PDR_AL(c->beta, m);
+    PDR_AL(c->zpart, c->nzpart);
+    PDR_AL(c->maxpart, c->nzpart);
+    PDR_AL(c->arcpart, 3 * (size_t)m);
+    PDR_AL(c->resout, 8);
+    PDR_AL(c->zlog, pdr::kZLogCap);
+    PDR_AL(c->ctrl, 1);
+#undef PDR_AL
+    e = hipHostMalloc((void **)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_res, 8 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return oom_or_dev(e, "hipHostMalloc");
+
+    // ---- initial state: f = 0, beta = beta_init, t = 0, z_prev = +inf (Algorithms 1, 3)
+    const size_t mK = (size_t)m * c->Kp;
+    void *f = cur_f(c);
+    e = hipMemsetAsync(f, 0, mK * (c->precision == PDR_FP64 ? 8 : 4), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->Fsum, 0, (size_t)(m ? m : 1) * 8, c->stream);
+    if (e != hipSuccess) return oom_or_dev(e, "hipMemsetAsync");
+    {
+        std::vector<double> b(m > 0 ? m : 1, opt.agd.beta_init);
+        e = hipMemcpyAsync(c->beta, b.data(), b.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return oom_or_dev(e, "beta upload");
+        std::memset(c->h_ctrl, 0, sizeof(Ctrl));
+        c->h_ctrl->z_prev = std::numeric_limits<double>::infinity();
+        e = hipMemcpyAsync(c->ctrl, c->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return oom_or_dev(e, "state upload");
+    }
+    *out = c;
+    return PDR_OK;
+}
+
+pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_target)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (max_sweeps < 0) return fail(c, PDR_ERR_INVALID, "max_sweeps must be >= 0");
+    if (std::isnan(eps_obj) || std::isnan(z_target))
+        return fail(c, PDR_ERR_INVALID, "eps_obj and z_target must not be NaN");
+    const bool fp64 = c->precision == PDR_FP64;
+    void *f = cur_f(c);
+    void *h = cur_h(c);
+    PDR_CHECK(c, pdr::launch_begin(c->ctrl, eps_obj, z_target, c->stream));
+    const bool poll = eps_obj > 0.0 || z_target > 0.0;
+    int64_t batch = 16;
+    int64_t since = 0;
+    const pdr::AgdParams prm{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
+                             c->agd.inc_period};
+    for (int64_t s = 0; s < max_sweeps; ++s) {
+        PDR_CHECK(c, pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, c->stream));
+        PDR_CHECK(c, pdr::launch_reduce(c->g, c->zpart, pdr::height_blocks(c->g, fp64 ? 8 : 4),
+                                        c->Fsum, c->ctrl, c->zlog, c->stream));
+        if (c->method == PDR_ESO)
+            PDR_CHECK(c, pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream));
+        else
+            PDR_CHECK(c, pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
+                                         c->ctrl, c->stream));
+        if (poll && ++since >= batch && s + 1 < max_sweeps) {
+            since = 0;
+            if (batch < 1024) batch *= 2;
+            st = sync_ctrl(c);
+            if (st != PDR_OK) return st;
+            if (c->h_ctrl->stopped) break;
+        }
+    }
+    return PDR_OK;
+}
+
+pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (sweeps < 0 || !kernel_ms) return fail(c, PDR_ERR_INVALID, "bad arguments");
+    const bool fp64 = c->precision == PDR_FP64;
+    void *f = cur_f(c);
+    void *h = cur_h(c);
+    const pdr::AgdParams prm{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
+                             c->agd.inc_period};
+    constexpr int B = 64;  // sweeps per batch of events
+    hipEvent_t ev[B][4];
+    for (int q = 0; q < B; ++q)
+        for (int r = 0; r < 4; ++r) PDR_CHECK(c, hipEventCreate(&ev[q][r]));
+    double tot[3] = {0.0, 0.0, 0.0};
+    hipError_t err = pdr::launch_begin(c->ctrl, 0.0, 0.0, c->stream);
+    for (int64_t s0 = 0; s0 < sweeps && err == hipSuccess; s0 += B) {
+        const int nb = (int)std::min<int64_t>(B, sweeps - s0);
+        for (int q = 0; q < nb && err == hipSuccess; ++q) {
+            err = hipEventRecord(ev[q][0], c->stream);
+            if (err == hipSuccess)
+                err = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[q][1], c->stream);
+            if (err == hipSuccess)
+                err = pdr::launch_reduce(c->g, c->zpart, pdr::height_blocks(c->g, fp64 ? 8 : 4),
+                                         c->Fsum, c->ctrl, c->zlog, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[q][2], c->stream);
+            if (err == hipSuccess)
+                err = c->method == PDR_ESO
+                          ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream)
+                          : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
+                                            c->ctrl, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[q][3], c->stream);
+        }
+        if (err == hipSuccess) err = hipEventSynchronize(ev[nb - 1][3]);
+        for (int q = 0; q < nb && err == hipSuccess; ++q)
+            for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+                float ms = 0.0f;
+                err = hipEventElapsedTime(&ms, ev[q][r], ev[q][r + 1]);
+                tot[r] += ms;
+            }
+    }
+    for (int q = 0; q < B; ++q)
+        for (int r = 0; r < 4; ++r) (void)hipEventDestroy(ev[q][r]);
+    PDR_CHECK(c, err);
+    for (int r = 0; r < 3; ++r) kernel_ms[r] = tot[r];
+    return PDR_OK;
+}
+
+pdr_status pdr_residual(pdr_ctx *c, pdr_residual_t *out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!out) return fail(c, PDR_ERR_INVALID, "out is NULL");
+    const bool fp64 = c->precision == PDR_FP64;
+    void *f = cur_f(c);
+    PDR_CHECK(c, pdr::launch_height_resid(c->g, fp64, f, c->h64, c->zpart, c->maxpart, c->stream));
+    PDR_CHECK(c, pdr::launch_resid(c->g, fp64, f, c->h64, c->Fsum, c->zpart,
+                                   pdr::height_blocks(c->g, fp64 ? 8 : 4), c->maxpart, c->arcpart,
+                                   c->resout, c->stream));
+    PDR_CHECK(c, hipMemcpyAsync(c->h_res, c->resout, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+    st = sync_ctrl(c);
+    if (st != PDR_OK) return st;
+    const double *r = c->h_res;
+    out->z = r[0];
+    out->z_psi = r[1];
+    out->z_h = r[2];
+    out->kkt_sq = r[3];
+    out->max_abs_excess = r[4];
+    out->max_congestion = r[5];
+    out->farkas_gap = r[6];
+    out->farkas_tol = r[7];
+    out->sweeps_done = c->h_ctrl->t;
+    out->evaluations = c->h_ctrl->evals;
+    out->stopped = c->h_ctrl->stopped;
+    if (r[6] > r[7])
+        out->verdict = PDR_INFEASIBLE;
+    else if (r[0] <= c->z_feasible_tol)
+        out->verdict = PDR_FEASIBLE;
+    else
+        out->verdict = PDR_UNDECIDED;
+    if (!std::isfinite(r[0]) || c->h_ctrl->numeric)
+        return fail(c, PDR_ERR_NUMERIC, "the objective is not finite");
+    return PDR_OK;
+}
+
+pdr_status pdr_flows(pdr_ctx *c, double *host_out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!host_out) return fail(c, PDR_ERR_INVALID, "host_out is NULL");
+    if (c->m == 0) return PDR_OK;
+    const size_t K = c->K, Kp = c->Kp, m = c->m;
+    if (c->precision == PDR_FP64) {
+        PDR_CHECK(c, hipMemcpy2DAsync(host_out, K * 8, c->f64, Kp * 8, K * 8, m,
+                                      hipMemcpyDeviceToHost, c->stream));
+        PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(m * K);
+        PDR_CHECK(c, hipMemcpy2DAsync(tmp.data(), K * 4, c->f32, Kp * 4, K * 4, m,
+                                      hipMemcpyDeviceToHost, c->stream));
+        PDR_CHECK(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < m * K; ++q) host_out[q] = (double)tmp[q];
+    }
+    return PDR_OK;
+}
+
+pdr_status pdr_flows_device(pdr_ctx *c, void *dev_out, int32_t fp64)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!dev_out) return fail(c, PDR_ERR_INVALID, "dev_out is NULL");
+    if (c->m == 0) return PDR_OK;
+    PDR_CHECK(c, pdr::launch_unpad(c->g, cur_f(c), c->precision == PDR_FP64, dev_out, fp64 != 0,
+                                   c->stream));
+    return PDR_OK;
+}
+
+pdr_status pdr_heights(pdr_ctx *c, double *host_out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!host_out) return fail(c, PDR_ERR_INVALID, "host_out is NULL");
+    const bool fp64 = c->precision == PDR_FP64;
+    PDR_CHECK(c, pdr::launch_height_resid(c->g, fp64, cur_f(c), c->h64, c->zpart, c->maxpart,
+                                          c->stream));
+    const size_t K = c->K, Kp = c->Kp;
+    PDR_CHECK(c, hipMemcpy2DAsync(host_out, K * 8, c->h64, Kp * 8, K * 8, (size_t)c->n,
+                                  hipMemcpyDeviceToHost, c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+pdr_status pdr_learning_rates(pdr_ctx *c, double *host_out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!host_out) return fail(c, PDR_ERR_INVALID, "host_out is NULL");
+    if (c->m == 0) return PDR_OK;
+    PDR_CHECK(c, hipMemcpyAsync(host_out, c->beta, (size_t)c->m * 8, hipMemcpyDeviceToHost,
+                                c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (count < 0 || first < 0 || (count > 0 && !host_out))
+        return fail(c, PDR_ERR_INVALID, "bad z log range");
+    st = sync_ctrl(c);
+    if (st != PDR_OK) return st;
+    const int64_t evals = c->h_ctrl->evals;
+    if (first + count > evals || first < evals - pdr::kZLogCap)
+        return fail(c, PDR_ERR_INVALID, "z log range not available");
+    int64_t done = 0;
+    while (done < count) {
+        const int64_t pos = (first + done) & (pdr::kZLogCap - 1);
+        int64_t len = std::min<int64_t>(count - done, pdr::kZLogCap - pos);
+        PDR_CHECK(c, hipMemcpyAsync(host_out + done, c->zlog + pos, (size_t)len * 8,
+                                    hipMemcpyDeviceToHost, c->stream));
+        done += len;
+    }
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (precision != PDR_FP64 && precision != PDR_FP32_BULK)
+        return fail(c, PDR_ERR_INVALID, "unknown precision");
+    if (precision == c->precision) return PDR_OK;
+    Tiling tl;
+    st = choose_tiling(c, precision, &tl);
+    if (st != PDR_OK) return st;
+    st = ensure_buffers(c, precision);
+    if (st != PDR_OK) return st;
+    const int64_t mK = (int64_t)c->m * c->Kp;
+    if (precision == PDR_FP64)
+        PDR_CHECK(c, pdr::launch_convert(c->f32, false, c->f64, true, mK, c->stream));
+    else
+        PDR_CHECK(c, pdr::launch_convert(c->f64, true, c->f32, false, mK, c->stream));
+    c->precision = precision;
+    c->tiling = tl;
+    PDR_CHECK(c, pdr::launch_rowsum(c->g, precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
+                                    c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    return PDR_OK;
+}
+
+pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, int64_t t,
+                         double z_prev)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!f && c->m > 0) return fail(c, PDR_ERR_INVALID, "f is NULL");
+    if (t < 0) return fail(c, PDR_ERR_INVALID, "t must be >= 0");
+    if (std::isnan(z_prev)) return fail(c, PDR_ERR_INVALID, "z_prev is NaN");
+    const size_t mK = (size_t)c->m * c->K;
+    for (size_t q = 0; q < mK; ++q)
+        if (!finite_nonneg(f[q])) return fail(c, PDR_ERR_INVALID, "flows must be finite and >= 0");
+    if (beta)
+        for (int32_t e = 0; e < c->m; ++e)
+            if (!(beta[e] > 0) || !std::isfinite(beta[e]))
+                return fail(c, PDR_ERR_INVALID, "learning rates must be finite and > 0");
+    if (c->m > 0) {
+        double *staging = nullptr;
+        hipError_t e = hipMalloc((void **)&staging, mK * 8);
+        if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (staging)");
+        PDR_CHECK(c, e);
+        e = hipMemcpyAsync(staging, f, mK * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = pdr::launch_pad(c->g, staging, cur_f(c), c->precision == PDR_FP64, c->stream);
+        if (e == hipSuccess)
+            e = pdr::launch_rowsum(c->g, c->precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
+                                   c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(staging);
+        PDR_CHECK(c, e);
+        if (beta)
+            PDR_CHECK(c, hipMemcpyAsync(c->beta, beta, (size_t)c->m * 8, hipMemcpyHostToDevice,
+                                        c->stream));
+    }
+    st = sync_ctrl(c);
+    if (st != PDR_OK) return st;
+    c->h_ctrl->t = t;
+    c->h_ctrl->z_prev = z_prev;
+    c->h_ctrl->stopped = 0;
+    c->h_ctrl->numeric = 0;
+    return push_ctrl(c);
+}
+
+pdr_status pdr_tiling(const pdr_ctx *c, int32_t *lanes_per_arc, int32_t *vec_per_lane, int32_t *Kp)
+{
+    if (!c) return PDR_ERR_INVALID;
+    if (lanes_per_arc) *lanes_per_arc = c->tiling.lanes;
+    if (vec_per_lane) *vec_per_lane = c->tiling.nv;
+    if (Kp) *Kp = c->Kp;
+    return PDR_OK;
+}
+
+void pdr_destroy(pdr_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal interface between the host library (pdr_api.cpp) and the HIP
+// kernels (pdr_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdr {
+
+// Device-resident run control and scalar state, read and written by the
+// kernels so that a sweep never needs a host round trip.
+struct Ctrl {
+    int32_t stopped;     // the stop test fired in the current pdr_sweep call
+    int32_t numeric;     // the objective was non-finite
+    int64_t t;           // iteration counter: arc updates applied so far
+    int64_t t_pass;      // iteration index used by the current pass's arc update
+    int64_t evals;       // number of objective evaluations logged
+    double z_prev;       // previous objective (stop test of Algorithm 1)
+    double eps_obj;      // stop if |z - z_prev| < eps_obj (when > 0)
+    double z_target;     // stop if z <= z_target (when > 0)
+    double z, z_psi, z_h;  // last evaluated objective and its two parts
+};
+
+constexpr int64_t kZLogCap = int64_t(1) << 20;
+
+// Graph and instance arrays in device memory.
+struct DevGraph {
+    int32_t n, m, K, Kp;
+    const int32_t *row_ptr;  // n+1: out-arcs of i are [row_ptr[i], row_ptr[i+1])
+    const int32_t *tails;    // m
+    const int32_t *heads;    // m
+    const int32_t *in_ptr;   // n+1: in-arcs of i are in_idx[in_ptr[i] .. in_ptr[i+1])
+    const int32_t *in_idx;   // m, ascending arc ids per head
+    const int32_t *deg;      // n: in-degree + out-degree
+    const int32_t *inj_ptr;  // n+1: injections of vertex i
+    const int32_t *inj_k;    // 2K: commodity of each injection
+    const double *inj_val;   // 2K: +d_k at s_k, -d_k at t_k
+    const double *u;         // m capacities
+    const int32_t *s, *t;    // K
+    const double *d;         // K
+};
+
+struct AgdParams {
+    double beta_min, beta_max, alpha_inc, alpha_dec;
+    int32_t inc_period;
+};
+
+// Arc-kernel tiling: `lanes` lanes cooperate on one arc, each holding up to
+// `nv` 16-byte vectors of the arc's commodity row in registers.
+struct Tiling {
+    int lanes;
+    int nv;
+};
+
+bool tiling_supported(int lanes, int nv);
+int64_t height_blocks(const DevGraph &g, int elem_bytes);
+
+// Launchers; each returns the launch status.
+hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st);
+hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
+                         const Ctrl *ctrl, bool check_stop, hipStream_t st);
+hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, double *h64,
+                               double *zpart, double *maxpart, hipStream_t st);
+hipError_t launch_reduce(const DevGraph &g, const double *zpart, int64_t nzpart,
+                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st);
+hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
+                      double *Fsum, const Ctrl *ctrl, hipStream_t st);
+hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
+                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl,
+                      hipStream_t st);
+hipError_t launch_rowsum(const DevGraph &g, bool fp64, Tiling tl, const void *f, double *Fsum,
+                         hipStream_t st);
+// Residual report: per-arc partials then one final reduction into out[8].
+hipError_t launch_resid(const DevGraph &g, bool fp64, const void *f, const double *h64,
+                        const double *Fsum, const double *zpart, int64_t nzpart,
+                        const double *maxpart, double *arcpart, double *out,
+                        hipStream_t st);
+hipError_t launch_convert(const void *src, bool src_fp64, void *dst, bool dst_fp64,
+                          int64_t count, hipStream_t st);
+// Unpadded copy of flows: dst[e*K + k] = f[e*Kp + k].
+hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst, bool dst_fp64,
+                        hipStream_t st);
+hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64,
+                      hipStream_t st);
+
+}  // namespace pdr

@@ -1,0 +1,841 @@
+// HIP kernels of one PDR sweep for gfx950 (MI355X).
+//
+// Data layout in HBM (all row-major, commodity-contiguous, rows padded to Kp):
+//   f[e * Kp + k]  pseudo-flow of commodity k on arc e (FP64 or FP32)
+//   h[i * Kp + k]  height of commodity k at vertex i (same precision as f)
+//   Fsum[e]        FP64 sum over k of the stored f[e, :] (gives psi_e)
+// Padded entries (k >= K) are zero and stay zero under both arc updates.
+//
+// A sweep is three launches on one stream:
+//   k_height  excess -> height (Expressions 2-4), one thread per 16-byte
+//             vector of a vertex row; FP64 accumulation; per-block partials
+//             of sum Delta * h for the objective.
+//   k_reduce  objective z (Algorithm 1) from those partials and Fsum; z log;
+//             the stop test; the iteration counter. One block.
+//   k_eso / k_agd  every arc in parallel (Expression 14 / Algorithm 3). A
+//             group of L lanes owns one arc and holds its row in registers;
+//             per-arc sums are FP64 group reductions with a fixed tree, so
+//             the results do not depend on scheduling.
+// No kernel uses atomics; every reduction order is fixed.
+#include <math.h>
+
+#include "pdr_internal.h"
+
+namespace pdr {
+
+template <typename T>
+struct VecT;
+template <>
+struct VecT<double> {
+    static constexpr int N = 2;
+};
+template <>
+struct VecT<float> {
+    static constexpr int N = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&v)[VecT<T>::N])
+{
+    if constexpr (sizeof(T) == 8) {
+        const double2 x = *reinterpret_cast<const double2 *>(p);
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        const float4 x = *reinterpret_cast<const float4 *>(p);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&v)[VecT<T>::N])
+{
+    if constexpr (sizeof(T) == 8) {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    } else {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs. Remap so that each XCD
+// works through one contiguous range of logical blocks; consecutive arcs share
+// their tail row of h, which then stays in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    constexpr int64_t NX = 8;
+    const int64_t q = nb / NX, r = nb % NX;
+    const int64_t x = b % NX, idx = b / NX;
+    return x * q + (x < r ? x : r) + idx;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Largest number of values reduced at once by one group_sum call.
+constexpr int kRedMax = 4;
+
+// Sum of N values over the L lanes of a group; every lane receives the same
+// bits (butterfly partners add the same two operands; the cross-wave step
+// sums the wave totals in wave order). For L > 64 the group is the whole
+// block and `lds` holds 2 * kRedMax * (L / 64) doubles: two halves used
+// alternately, so a wave that runs ahead into the next reduction never
+// overwrites values another wave is still reading.
+template <int L, int N>
+__device__ __forceinline__ void group_sum(double (&v)[N], double *lds, int &phase)
+{
+    static_assert(N <= kRedMax, "too many values in one reduction");
+    if constexpr (L == 1) {
+        return;
+    } else if constexpr (L <= 64) {
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < N; ++q) v[q] += __shfl_xor(v[q], off, L);
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+        constexpr int NW = L / 64;
+        double *buf = lds + phase * (kRedMax * NW);
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) buf[q * NW + w] = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double s = buf[q * NW];
+#pragma unroll
+            for (int ww = 1; ww < NW; ++ww) s += buf[q * NW + ww];
+            v[q] = s;
+        }
+        phase ^= 1;
+    }
+}
+
+// ----------------------------------------------------------------- control
+__global__ void k_begin(Ctrl *ctrl, double eps_obj, double z_target)
+{
+    if (threadIdx.x == 0) {
+        ctrl->stopped = 0;
+        ctrl->eps_obj = eps_obj;
+        ctrl->z_target = z_target;
+    }
+}
+
+// ----------------------------------------------------------------- excess -> height
+// Thread (i, q) computes Delta_ik = sum_in f - sum_out f + hatDelta_ik for the
+// V commodities of vector q of vertex i, then h = Delta / delta_i.
+// RESID: write FP64 heights to h64 and also the per-block max |Delta|.
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
+                                                T *__restrict__ h, double *__restrict__ h64,
+                                                double *__restrict__ zpart,
+                                                double *__restrict__ maxpart,
+                                                const Ctrl *__restrict__ ctrl, int check_stop)
+{
+    if (check_stop && ctrl->stopped) return;
+    constexpr int V = VecT<T>::N;
+    __shared__ double sh[8];
+    const int nvec = g.Kp / V;
+    const int64_t Kp = g.Kp;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double zs = 0.0, mx = 0.0;
+    if (gid < (int64_t)g.n * nvec) {
+        const int i = (int)(gid / nvec);
+        const int k0 = (int)(gid - (int64_t)i * nvec) * V;
+        double acc[V];
+#pragma unroll
+        for (int w = 0; w < V; ++w) acc[w] = 0.0;
+        const int p0 = g.in_ptr[i], p1 = g.in_ptr[i + 1];
+        for (int p = p0; p < p1; ++p) {
+            const int64_t e = g.in_idx[p];
+            T x[V];
+            load_vec(f + e * Kp + k0, x);
+#pragma unroll
+            for (int w = 0; w < V; ++w) acc[w] += (double)x[w];
+        }
+        const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+        for (int e = e0; e < e1; ++e) {
+            T x[V];
+            load_vec(f + (int64_t)e * Kp + k0, x);
+#pragma unroll
+            for (int w = 0; w < V; ++w) acc[w] -= (double)x[w];
+        }
+        const int j0 = g.inj_ptr[i], j1 = g.inj_ptr[i + 1];
+        for (int p = j0; p < j1; ++p) {
+            const int k = g.inj_k[p] - k0;
+            const double val = g.inj_val[p];
+#pragma unroll
+            for (int w = 0; w < V; ++w)
+                if (w == k) acc[w] += val;
+        }
+        const int dg = g.deg[i];
+        T hv[V];
+        double hd[V];
+#pragma unroll
+        for (int w = 0; w < V; ++w) {
+            const double hh = dg > 0 ? acc[w] / (double)dg : 0.0;
+            hd[w] = hh;
+            hv[w] = (T)hh;
+            zs += acc[w] * hh;
+            if (RESID) mx = fmax(mx, fabs(acc[w]));
+        }
+        if constexpr (RESID) {
+            double *dst = h64 + (int64_t)i * Kp + k0;
+#pragma unroll
+            for (int w = 0; w < V; w += 2)
+                *reinterpret_cast<double2 *>(dst + w) = make_double2(hd[w], hd[w + 1]);
+        } else {
+            store_vec(h + (int64_t)i * Kp + k0, hv);
+        }
+    }
+    zs = wave_sum(zs);
+    if (RESID) mx = wave_max(mx);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = zs;
+        sh[4 + w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        zpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        if (RESID) maxpart[blockIdx.x] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+    }
+}
+
+// ----------------------------------------------------------------- objective + stop test
+// z = 1/2 sum_e max(0, Fsum_e - u_e)^2 + 1/2 sum_{i,k} Delta_ik h_ik (Algorithm 1).
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int64_t nz,
+                                                 const double *__restrict__ Fsum,
+                                                 const double *__restrict__ u, int m,
+                                                 Ctrl *__restrict__ ctrl, double *__restrict__ zlog)
+{
+    if (ctrl->stopped) return;
+    __shared__ double sh[2][16];
+    double a = 0.0, b = 0.0;
+    for (int64_t q = threadIdx.x; q < nz; q += 1024) a += zpart[q];
+    for (int q = threadIdx.x; q < m; q += 1024) {
+        const double over = Fsum[q] - u[q];
+        if (over > 0.0) b += over * over;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0.0, B = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            A += sh[0][q];
+            B += sh[1][q];
+        }
+        const double zh = 0.5 * A, zp = 0.5 * B, z = zp + zh;
+        const int64_t ev = ctrl->evals;
+        zlog[ev & (kZLogCap - 1)] = z;
+        ctrl->evals = ev + 1;
+        ctrl->z = z;
+        ctrl->z_psi = zp;
+        ctrl->z_h = zh;
+        const bool fin = isfinite(z);
+        const bool stop = !fin || (ctrl->eps_obj > 0.0 && fabs(z - ctrl->z_prev) < ctrl->eps_obj) ||
+                          (ctrl->z_target > 0.0 && z <= ctrl->z_target);
+        if (!fin) ctrl->numeric = 1;
+        if (stop) {
+            ctrl->stopped = 1;
+        } else {
+            ctrl->z_prev = z;
+            ctrl->t_pass = ctrl->t;
+            ctrl->t = ctrl->t + 1;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- arc kernels
+template <int L>
+struct ArcShape {
+    static constexpr int BS = L > 64 ? L : 256;  // block size
+    static constexpr int GPB = BS / L;           // arcs per block
+    static constexpr int NW = L > 64 ? L / 64 : 1;
+};
+
+// PDR-ESO arc update: the exact minimiser of the edge subproblem
+// (Expression 14). With c_k = ((h_ik + f_k) - (h_jk - f_k)) / 2 (Algorithm 2),
+// the new flows are f'_k = max(0, c_k - psi/2) where psi = 0 if
+// sum_k max(0, c_k) <= u, and otherwise psi is the root of
+// psi = sum_k max(0, c_k - psi/2) - u. The root is found without sorting by
+// the finite active-set iteration of Michelot (1986) for projections onto a
+// simplex: with A = {k: c_k > 0}, repeat psi = (sum_A c - u) / (1 + |A|/2),
+// A <- {k in A: c_k > psi/2} until A is unchanged. Each pass is one group
+// reduction of (sum, count) over the register-resident c.
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restrict__ f,
+                                                          const T *__restrict__ h,
+                                                          double *__restrict__ Fsum,
+                                                          const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    constexpr int V = VecT<T>::N;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    int phase = 0;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t e = blk * S::GPB + grp;
+    if (L <= 64 && e >= g.m) return;
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    const T *fe = f + e * Kp;
+    const T *hi = h + (int64_t)g.tails[e] * Kp;
+    const T *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+
+    T c[NV][V];
+    double red[2] = {0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            T a[V], b[V], x[V];
+            load_vec(fe + q * V, x);
+            load_vec(hi + q * V, a);
+            load_vec(hj + q * V, b);
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const T cc = (T)0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
+                c[v][w] = cc;
+                if (cc > (T)0) {
+                    red[0] += (double)cc;
+                    red[1] += 1.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < V; ++w) c[v][w] = (T)0;
+        }
+    }
+    group_sum<L, 2>(red, lds, phase);
+    double Ssum = red[0], P = red[1];
+    double psi = 0.0;
+    if (Ssum > u) {
+        double theta = 0.0;
+        for (;;) {
+            psi = (Ssum - u) / (1.0 + 0.5 * P);
+            const double th = fmax(theta, 0.5 * psi);
+            double r2[2] = {0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double cc = (double)c[v][w];
+                    if (cc > th) {
+                        r2[0] += cc;
+                        r2[1] += 1.0;
+                    }
+                }
+            group_sum<L, 2>(r2, lds, phase);
+            if (r2[1] == P) break;  // active set unchanged: psi is the root
+            Ssum = r2[0];
+            P = r2[1];
+            theta = th;
+        }
+    }
+    const double half = 0.5 * psi;
+    double fs[1] = {0.0};
+    T *fo = f + e * Kp;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            T o[V];
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const double val = (double)c[v][w] - half;
+                o[w] = (T)(val > 0.0 ? val : 0.0);
+                fs[0] += (double)o[w];
+            }
+            store_vec(fo + q * V, o);
+        }
+    }
+    group_sum<L, 1>(fs, lds, phase);
+    if (lane == 0) Fsum[e] = fs[0];
+}
+
+// PDR-AGD arc update (Algorithm 3): phi_k = h_ik - h_jk - psi,
+// df_k = max(-f_k, beta phi_k); the step is kept iff the exact change of the
+// edge subproblem objective (Expression 13, optimal slack),
+// dz = 1/2[(F + sum df - u)_+^2 - psi^2] + sum_k (df_k^2 - df_k (h_ik - h_jk)),
+// is <= 0; otherwise beta <- max(beta_min, alpha_dec beta). Every inc_period
+// iterations beta <- min(beta_max, alpha_inc beta).
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restrict__ f,
+                                                          const T *__restrict__ h,
+                                                          double *__restrict__ Fsum,
+                                                          double *__restrict__ beta,
+                                                          AgdParams prm,
+                                                          const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    constexpr int V = VecT<T>::N;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    int phase = 0;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t e = blk * S::GPB + grp;
+    if (L <= 64 && e >= g.m) return;
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    const T *fe = f + e * Kp;
+    const T *hi = h + (int64_t)g.tails[e] * Kp;
+    const T *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+    const double F = Fsum[e];
+    const double psi = F > u ? F - u : 0.0;
+    const double b = beta[e];
+
+    T fv[NV][V], gv[NV][V];
+    double red[3] = {0.0, 0.0, 0.0};  // sum df, sum (df^2 - df g), sum of stepped values
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            T a[V], bb[V], x[V];
+            load_vec(fe + q * V, x);
+            load_vec(hi + q * V, a);
+            load_vec(hj + q * V, bb);
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const T gg = a[w] - bb[w];
+                fv[v][w] = x[w];
+                gv[v][w] = gg;
+                const double fx = (double)x[w];
+                const double step = b * ((double)gg - psi);
+                const double df = step > -fx ? step : -fx;
+                red[0] += df;
+                red[1] += df * df - df * (double)gg;
+                red[2] += (double)(T)(fx + df);
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                fv[v][w] = (T)0;
+                gv[v][w] = (T)0;
+            }
+        }
+    }
+    group_sum<L, 3>(red, lds, phase);
+    const double over = F + red[0] - u;
+    const double npsi = over > 0.0 ? over : 0.0;
+    const double dz = 0.5 * (npsi * npsi - psi * psi) + red[1];
+    const bool accept = dz <= 0.0;
+    if (accept) {
+        T *fo = f + e * Kp;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int q = v * L + lane;
+            if (q < nvec) {
+                T o[V];
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double fx = (double)fv[v][w];
+                    const double step = b * ((double)gv[v][w] - psi);
+                    const double df = step > -fx ? step : -fx;
+                    o[w] = (T)(fx + df);
+                }
+                store_vec(fo + q * V, o);
+            }
+        }
+    }
+    if (lane == 0) {
+        double nb = b;
+        if (!accept) nb = fmax(prm.beta_min, nb * prm.alpha_dec);
+        if (prm.inc_period > 0 && (ctrl->t_pass % prm.inc_period) == 0)
+            nb = fmin(prm.beta_max, nb * prm.alpha_inc);
+        beta[e] = nb;
+        if (accept) Fsum[e] = red[2];
+    }
+}
+
+// Fsum[e] = sum_k f[e, k] with the same lane layout and reduction tree as the
+// arc kernels (so a restored state continues bit for bit).
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T *__restrict__ f,
+                                                             double *__restrict__ Fsum)
+{
+    constexpr int V = VecT<T>::N;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    int phase = 0;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t e = blk * S::GPB + grp;
+    if (L <= 64 && e >= g.m) return;
+    const int nvec = g.Kp / V;
+    const T *fe = f + e * (int64_t)g.Kp;
+    double fs[1] = {0.0};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            T x[V];
+            load_vec(fe + q * V, x);
+#pragma unroll
+            for (int w = 0; w < V; ++w) fs[0] += (double)x[w];
+        }
+    }
+    group_sum<L, 1>(fs, lds, phase);
+    if (lane == 0) Fsum[e] = fs[0];
+}
+
+// ----------------------------------------------------------------- residual report
+// Per arc: sum_k rho_k^2 (rho = phi if f > 0 else max(0, phi)), u_e l_e with
+// l_e = max(0, max_k (h_ik - h_jk)), and psi_e. One block per arc.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_arc(DevGraph g, const T *__restrict__ f,
+                                                   const double *__restrict__ h64,
+                                                   const double *__restrict__ Fsum,
+                                                   double *__restrict__ arcpart)
+{
+    __shared__ double sh[8];
+    const int e = blockIdx.x;
+    const int64_t Kp = g.Kp;
+    const double *hi = h64 + (int64_t)g.tails[e] * Kp;
+    const double *hj = h64 + (int64_t)g.heads[e] * Kp;
+    const T *fe = f + (int64_t)e * Kp;
+    const double u = g.u[e];
+    const double F = Fsum[e];
+    const double psi = F > u ? F - u : 0.0;
+    double kkt = 0.0, lmax = 0.0;
+    for (int k = threadIdx.x; k < g.K; k += 256) {
+        const double gg = hi[k] - hj[k];
+        const double phi = gg - psi;
+        const double rho = (double)fe[k] > 0.0 ? phi : (phi > 0.0 ? phi : 0.0);
+        kkt += rho * rho;
+        lmax = fmax(lmax, gg);
+    }
+    kkt = wave_sum(kkt);
+    lmax = wave_max(lmax);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = kkt;
+        sh[4 + w] = lmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        arcpart[e] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        arcpart[g.m + e] = u * fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+        arcpart[2 * (int64_t)g.m + e] = psi;
+    }
+}
+
+// out: z, z_psi, z_h, kkt_sq, max|Delta|, max psi, Farkas gap G, margin tau.
+__global__ __launch_bounds__(1024) void k_resid_final(DevGraph g, const double *__restrict__ h64,
+                                                      const double *__restrict__ zpart,
+                                                      int64_t nz,
+                                                      const double *__restrict__ maxpart,
+                                                      const double *__restrict__ arcpart,
+                                                      double *__restrict__ out)
+{
+    __shared__ double sh[8][16];
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // zh, zpsi, kkt, ul, maxD, maxpsi, dh, dh_abs
+    for (int64_t q = threadIdx.x; q < nz; q += 1024) {
+        a[0] += zpart[q];
+        a[4] = fmax(a[4], maxpart[q]);
+    }
+    for (int q = threadIdx.x; q < g.m; q += 1024) {
+        const double p = arcpart[2 * (int64_t)g.m + q];
+        a[1] += p * p;
+        a[2] += arcpart[q];
+        a[3] += arcpart[g.m + q];
+        a[5] = fmax(a[5], p);
+    }
+    const int64_t Kp = g.Kp;
+    for (int k = threadIdx.x; k < g.K; k += 1024) {
+        const double gg = h64[(int64_t)g.s[k] * Kp + k] - h64[(int64_t)g.t[k] * Kp + k];
+        a[6] += g.d[k] * gg;
+        a[7] += g.d[k] * fabs(gg);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = (q == 4 || q == 5) ? wave_max(a[q]) : wave_sum(a[q]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 8; ++q) sh[q][w] = a[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[8];
+        for (int q = 0; q < 8; ++q) {
+            double s = sh[q][0];
+            for (int ww = 1; ww < 16; ++ww) s = (q == 4 || q == 5) ? fmax(s, sh[q][ww]) : s + sh[q][ww];
+            r[q] = s;
+        }
+        const double zh = 0.5 * r[0], zp = 0.5 * r[1];
+        out[0] = zp + zh;
+        out[1] = zp;
+        out[2] = zh;
+        out[3] = r[2];
+        out[4] = r[4];
+        out[5] = r[5];
+        out[6] = r[6] - r[3];
+        out[7] = 64.0 * 2.220446049250313e-16 * (r[7] + r[3]);
+    }
+}
+
+// ----------------------------------------------------------------- copies
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_convert(const S *__restrict__ src, D *__restrict__ dst,
+                                                 int64_t count)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * 256)
+        dst[q] = (D)src[q];
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_unpad(const S *__restrict__ f, D *__restrict__ dst,
+                                               int64_t m, int K, int Kp)
+{
+    const int64_t total = m * (int64_t)K;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * 256) {
+        const int64_t e = q / K;
+        const int k = (int)(q - e * K);
+        dst[q] = (D)f[e * Kp + k];
+    }
+}
+
+template <typename D>
+__global__ __launch_bounds__(256) void k_pad(const double *__restrict__ src, D *__restrict__ f,
+                                             int64_t m, int K, int Kp)
+{
+    const int64_t total = m * (int64_t)Kp;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * 256) {
+        const int64_t e = q / Kp;
+        const int k = (int)(q - e * Kp);
+        f[q] = k < K ? (D)src[e * K + k] : (D)0;
+    }
+}
+
+// ----------------------------------------------------------------- launchers
+static inline unsigned grid_for(int64_t work, int64_t cap = 1 << 20)
+{
+    int64_t b = (work + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+int64_t height_blocks(const DevGraph &g, int elem_bytes)
+{
+    const int V = 16 / elem_bytes;
+    const int64_t work = (int64_t)g.n * (g.Kp / V);
+    return work > 0 ? (work + 255) / 256 : 1;
+}
+
+hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st)
+{
+    k_begin<<<1, 64, 0, st>>>(ctrl, eps_obj, z_target);
+    return hipGetLastError();
+}
+
+hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
+                         const Ctrl *ctrl, bool check_stop, hipStream_t st)
+{
+    const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
+    if (fp64)
+        k_height<double, false><<<nb, 256, 0, st>>>(g, (const double *)f, (double *)h, nullptr,
+                                                    zpart, nullptr, ctrl, check_stop ? 1 : 0);
+    else
+        k_height<float, false><<<nb, 256, 0, st>>>(g, (const float *)f, (float *)h, nullptr, zpart,
+                                                   nullptr, ctrl, check_stop ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, double *h64,
+                               double *zpart, double *maxpart, hipStream_t st)
+{
+    const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
+    if (fp64)
+        k_height<double, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
+                                                   maxpart, nullptr, 0);
+    else
+        k_height<float, true><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart, maxpart,
+                                                  nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const DevGraph &g, const double *zpart, int64_t nzpart,
+                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
+{
+    k_reduce<<<1, 1024, 0, st>>>(zpart, nzpart, Fsum, g.u, g.m, ctrl, zlog);
+    return hipGetLastError();
+}
+
+#define PDR_TILINGS(X) \
+    X(1, 1) X(1, 2) X(1, 4) X(1, 8) \
+    X(2, 1) X(2, 2) X(2, 4) X(2, 8) \
+    X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
+    X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
+    X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
+    X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
+    X(64, 1) X(64, 2) X(64, 4) X(64, 8) \
+    X(128, 1) X(128, 2) X(128, 4) X(128, 8) \
+    X(256, 1) X(256, 2) X(256, 4) X(256, 8) \
+    X(512, 1) X(512, 2) X(512, 4) X(512, 8) \
+    X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 8)
+
+bool tiling_supported(int lanes, int nv)
+{
+#define PDR_SUP(L_, NV_) \
+    if (lanes == L_ && nv == NV_) return true;
+    PDR_TILINGS(PDR_SUP)
+#undef PDR_SUP
+    return false;
+}
+
+static inline unsigned arc_blocks(int64_t m, int L)
+{
+    const int BS = L > 64 ? L : 256;
+    const int64_t gpb = BS / L;
+    return (unsigned)((m + gpb - 1) / gpb);
+}
+
+hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
+                      double *Fsum, const Ctrl *ctrl, hipStream_t st)
+{
+    if (g.m == 0) return hipSuccess;
+#define PDR_ESO_CASE(L_, NV_)                                                                    \
+    if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
+        const unsigned nb = arc_blocks(g.m, L_);                                                 \
+        constexpr int BS = L_ > 64 ? L_ : 256;                                                   \
+        if (fp64)                                                                                \
+            k_eso<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h, Fsum,   \
+                                                      ctrl);                                     \
+        else                                                                                     \
+            k_eso<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h, Fsum, ctrl); \
+        return hipGetLastError();                                                                \
+    }
+    PDR_TILINGS(PDR_ESO_CASE)
+#undef PDR_ESO_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
+                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl, hipStream_t st)
+{
+    if (g.m == 0) return hipSuccess;
+#define PDR_AGD_CASE(L_, NV_)                                                                  \
+    if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
+        const unsigned nb = arc_blocks(g.m, L_);                                               \
+        constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
+        if (fp64)                                                                              \
+            k_agd<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h, Fsum, \
+                                                      beta, prm, ctrl);                        \
+        else                                                                                   \
+            k_agd<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h, Fsum,    \
+                                                     beta, prm, ctrl);                         \
+        return hipGetLastError();                                                              \
+    }
+    PDR_TILINGS(PDR_AGD_CASE)
+#undef PDR_AGD_CASE
+    return hipErrorInvalidValue;
+}
+
+// Row sums use the tiling of the arc kernels, chosen by the caller.
+hipError_t launch_rowsum(const DevGraph &g, bool fp64, Tiling tl, const void *f, double *Fsum,
+                         hipStream_t st)
+{
+    if (g.m == 0) return hipSuccess;
+#define PDR_ROW_CASE(L_, NV_)                                                                    \
+    if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
+        const unsigned nb = arc_blocks(g.m, L_);                                                 \
+        constexpr int BS = L_ > 64 ? L_ : 256;                                                   \
+        if (fp64)                                                                                \
+            k_rowsum<double, L_, NV_><<<nb, BS, 0, st>>>(g, (const double *)f, Fsum);            \
+        else                                                                                     \
+            k_rowsum<float, L_, NV_><<<nb, BS, 0, st>>>(g, (const float *)f, Fsum);              \
+        return hipGetLastError();                                                                \
+    }
+    PDR_TILINGS(PDR_ROW_CASE)
+#undef PDR_ROW_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_resid(const DevGraph &g, bool fp64, const void *f, const double *h64,
+                        const double *Fsum, const double *zpart, int64_t nzpart,
+                        const double *maxpart, double *arcpart, double *out, hipStream_t st)
+{
+    if (g.m > 0) {
+        if (fp64)
+            k_resid_arc<double><<<g.m, 256, 0, st>>>(g, (const double *)f, h64, Fsum, arcpart);
+        else
+            k_resid_arc<float><<<g.m, 256, 0, st>>>(g, (const float *)f, h64, Fsum, arcpart);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    k_resid_final<<<1, 1024, 0, st>>>(g, h64, zpart, nzpart, maxpart, arcpart, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, bool src_fp64, void *dst, bool dst_fp64, int64_t count,
+                          hipStream_t st)
+{
+    const unsigned nb = grid_for(count, 65536);
+    if (src_fp64 && dst_fp64)
+        k_convert<double, double><<<nb, 256, 0, st>>>((const double *)src, (double *)dst, count);
+    else if (src_fp64)
+        k_convert<double, float><<<nb, 256, 0, st>>>((const double *)src, (float *)dst, count);
+    else if (dst_fp64)
+        k_convert<float, double><<<nb, 256, 0, st>>>((const float *)src, (double *)dst, count);
+    else
+        k_convert<float, float><<<nb, 256, 0, st>>>((const float *)src, (float *)dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst, bool dst_fp64,
+                        hipStream_t st)
+{
+    const unsigned nb = grid_for((int64_t)g.m * g.K, 65536);
+    if (f_fp64 && dst_fp64)
+        k_unpad<double, double><<<nb, 256, 0, st>>>((const double *)f, (double *)dst, g.m, g.K, g.Kp);
+    else if (f_fp64)
+        k_unpad<double, float><<<nb, 256, 0, st>>>((const double *)f, (float *)dst, g.m, g.K, g.Kp);
+    else if (dst_fp64)
+        k_unpad<float, double><<<nb, 256, 0, st>>>((const float *)f, (double *)dst, g.m, g.K, g.Kp);
+    else
+        k_unpad<float, float><<<nb, 256, 0, st>>>((const float *)f, (float *)dst, g.m, g.K, g.Kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64, hipStream_t st)
+{
+    const unsigned nb = grid_for((int64_t)g.m * g.Kp, 65536);
+    if (f_fp64)
+        k_pad<double><<<nb, 256, 0, st>>>(src, (double *)f, g.m, g.K, g.Kp);
+    else
+        k_pad<float><<<nb, 256, 0, st>>>(src, (float *)f, g.m, g.K, g.Kp);
+    return hipGetLastError();
+}
+
+}  // namespace pdr

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol that
+include/pdr.h declares, and rejects invalid instances before touching a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2108_07549_amd as pdr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "pdr.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    assert set(syms) == set(pdr.EXPORTS), syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = pdr.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_default_options_are_the_papers_settings():
+    o = pdr.default_options()
+    assert o.method == pdr.ESO and o.precision == pdr.FP64
+    a = o.agd
+    assert (a.beta_init, a.beta_min, a.beta_max, a.alpha_inc, a.alpha_dec, a.inc_period) == \
+        (0.25, 0.0, 0.5, 2.0, 0.5, 10)
+    assert o.z_feasible_tol == 1e-8 and not o.stream
+
+
+def _good():
+    # 3 vertices, arcs 0->1, 1->2, 2->0; one commodity 0 -> 2
+    return dict(n=3, row_ptr=np.array([0, 1, 2, 3]), col=np.array([1, 2, 0]),
+                u=np.array([1.0, 1.0, 1.0]), s=np.array([0]), t=np.array([2]), d=np.array([0.5]))
+
+
+@pytest.mark.parametrize("mutate,fragment", [
+    (lambda a: a.update(n=0, row_ptr=np.array([0])), "n must be"),
+    (lambda a: a.update(s=np.array([], np.int32), t=np.array([], np.int32), d=np.array([])), "K must be"),
+    (lambda a: a.update(row_ptr=np.array([1, 1, 2, 3])), "row_ptr[0]"),
+    (lambda a: a.update(row_ptr=np.array([0, 2, 1, 3])), "non-decreasing"),
+    (lambda a: a.update(row_ptr=np.array([0, 1, 2, 2])), "row_ptr[n]"),
+    (lambda a: a.update(col=np.array([1, 3, 0])), "head out of range"),
+    (lambda a: a.update(col=np.array([0, 2, 0])), "self-loop"),
+    (lambda a: a.update(u=np.array([1.0, -1.0, 1.0])), "capacities"),
+    (lambda a: a.update(u=np.array([1.0, np.nan, 1.0])), "capacities"),
+    (lambda a: a.update(u=np.array([1.0, np.inf, 1.0])), "capacities"),
+    (lambda a: a.update(d=np.array([-0.5])), "demands"),
+    (lambda a: a.update(d=np.array([np.nan])), "demands"),
+    (lambda a: a.update(s=np.array([3])), "out of range"),
+    (lambda a: a.update(t=np.array([-1])), "out of range"),
+    (lambda a: a.update(t=np.array([0])), "s_k == t_k"),
+])
+def test_init_rejects_invalid_instances(mutate, fragment):
+    a = _good()
+    mutate(a)
+    with pytest.raises(pdr.PdrError) as ei:
+        pdr.Context(a["n"], a["row_ptr"], a["col"], a["u"], a["s"], a["t"], a["d"])
+    assert ei.value.status == 1 and fragment in ei.value.message
+    assert fragment in pdr.lib().pdr_last_error(None).decode()
+
+
+def test_init_rejects_isolated_commodity_endpoint():
+    # vertex 3 has no arcs: its height (Delta / degree) is undefined
+    with pytest.raises(pdr.PdrError) as ei:
+        pdr.Context(4, np.array([0, 1, 2, 3, 3]), np.array([1, 2, 0]), np.ones(3),
+                    np.array([0]), np.array([3]), np.array([1.0]))
+    assert ei.value.status == 1 and "degree 0" in ei.value.message
+
+
+@pytest.mark.parametrize("opts,fragment", [
+    (dict(method=7), "unknown method"),
+    (dict(precision=3), "unknown precision"),
+    (dict(method=pdr.AGD, agd=dict(beta_init=0.0)), "AGD parameters"),
+    (dict(method=pdr.AGD, agd=dict(alpha_dec=float("nan"))), "AGD parameters"),
+    (dict(z_feasible_tol=-1.0), "z_feasible_tol"),
+    (dict(lanes_per_arc=3), "tiling"),
+    (dict(lanes_per_arc=1, vec_per_lane=1), "tiling"),  # K=100 needs more than 1 x 1 vectors
+])
+def test_init_rejects_invalid_options(opts, fragment):
+    a = _good()
+    s = np.zeros(100, np.int32)
+    t = np.full(100, 2, np.int32)
+    with pytest.raises(pdr.PdrError) as ei:
+        pdr.Context(a["n"], a["row_ptr"], a["col"], a["u"], s, t, np.ones(100), **opts)
+    assert ei.value.status == 1 and fragment in ei.value.message
+
+
+def test_oversize_commodity_row_is_rejected():
+    a = _good()
+    K = 40000  # FP64 rows above 1024 lanes x 8 vectors x 2 values are not supported
+    with pytest.raises(pdr.PdrError) as ei:
+        pdr.Context(a["n"], a["row_ptr"], a["col"], a["u"], np.zeros(K, np.int32),
+                    np.full(K, 2, np.int32), np.ones(K))
+    assert ei.value.status == 1 and "tiling" in ei.value.message
+
+
+def test_null_context_calls_are_invalid():
+    L = pdr.lib()
+    assert L.pdr_sweep(None, 1, 0.0, 0.0) == 1
+    assert L.pdr_flows(None, None) == 1
+    assert L.pdr_residual(None, None) == 1
+    L.pdr_destroy(None)  # ignored
