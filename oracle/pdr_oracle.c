@@ -26,7 +26,8 @@
  *  - if rounding makes every interval test of Algorithm 2 fail, the largest
  *    p with 2 c_(p) > psi_p is taken (that predicate is monotone in p);
  *  - the AGD objective change is the exact change of the edge subproblem
- *    objective (Expression 13) with the optimal slack r >= 0;
+ *    objective (Expression 13) with the optimal slack r >= 0, evaluated in a
+ *    form free of cancellation (a difference of squares is factored);
  *  - the AGD periodic increase multiplies beta_ij by alpha_inc and caps it at
  *    beta_max, after the accept/reject step, including at t = 0.
  */
@@ -242,12 +243,21 @@ int orc_agd_edge(int32_t K, const double *hi, const double *hj, const double *fe
         fout[k] = df; /* hold the step until the decision */
         sum_df += df;
         /* change of the two height terms of Expression 13 for this commodity:
-         * 1/2[(h_i - df)^2 - h_i^2 + (h_j + df)^2 - h_j^2] = df^2 - df (h_i - h_j) */
-        quad += df * df - df * g;
+         * 1/2[(h_i - df)^2 - h_i^2 + (h_j + df)^2 - h_j^2] = df (df - (h_i - h_j)) */
+        quad += df * (df - g);
     }
-    double over = F + sum_df - u;
-    double new_psi = over > 0.0 ? over : 0.0;
-    double dz = 0.5 * (new_psi * new_psi - psi * psi) + quad;
+    /* change of the congestion term, 1/2[(F + S - u)_+^2 - (F - u)_+^2] with
+     * S = sum df. When the arc is over capacity before and after, it equals
+     * S (F - u + S/2) (difference of squares), which avoids cancelling two
+     * large squares when the step is small. */
+    double before = F - u, after = F + sum_df - u;
+    double dcong;
+    if (before > 0.0 && after > 0.0)
+        dcong = sum_df * (before + 0.5 * sum_df);
+    else
+        dcong = 0.5 * ((after > 0.0 ? after * after : 0.0) - (before > 0.0 ? before * before : 0.0));
+    double dz = dcong + quad;
+    (void)psi;
     int accept = dz <= 0.0;
     for (int32_t k = 0; k < K; ++k) fout[k] = accept ? fe[k] + fout[k] : fe[k];
     if (!accept) {
