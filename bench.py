@@ -50,15 +50,15 @@ def measured_traffic(key: str):
     return entry.get("bytes_per_launch")
 
 
-def time_variant(pdr, torch, inst, method, precision, steps, warmup):
+def time_variant(pdr, inst, method, precision, steps, warmup):
     """Warm up, then time exactly `steps` sweeps; returns timing and per-kernel ms."""
     ctx = pdr.Context.from_instance(inst, method=method, precision=precision)
     try:
         ctx.sweep(warmup)
-        torch.cuda.synchronize()
+        pdr.device_synchronize()
         t0 = time.perf_counter()
         kms = ctx.profile_sweeps(steps)
-        torch.cuda.synchronize()
+        pdr.device_synchronize()
         t1 = time.perf_counter()
         res = ctx.residual()
         tiling = ctx.tiling()
@@ -99,15 +99,13 @@ def main():
               f"(the multi-GPU sharding is a design, not a build).", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     import paper_2108_07549_amd as pdr
     from gen.instance import load_instance
 
     inst = load_instance(args.workload)
     print(f"[bench] {args.workload}: n {inst.n} m {inst.m} K {inst.K}; "
           f"{args.warmup} warmup + {args.steps} timed sweeps", file=sys.stderr, flush=True)
-    head = time_variant(pdr, torch, inst, pdr.ESO, pdr.FP64, args.steps, args.warmup)
+    head = time_variant(pdr, inst, pdr.ESO, pdr.FP64, args.steps, args.warmup)
     print(f"[bench] eso fp64: {head['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
 
     n, m, K = inst.n, inst.m, inst.K
@@ -146,7 +144,7 @@ def main():
         var = {}
         for name, meth, prec in (("agd_fp64", pdr.AGD, pdr.FP64), ("eso_fp32", pdr.ESO, pdr.FP32_BULK),
                                  ("agd_fp32", pdr.AGD, pdr.FP32_BULK)):
-            r = time_variant(pdr, torch, inst, meth, prec, args.steps, args.warmup)
+            r = time_variant(pdr, inst, meth, prec, args.steps, args.warmup)
             print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
             var[name] = dict(updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"],
                              kernel_ms_avg=r["kernel_ms_avg"], tiling=r["tiling"])

@@ -70,6 +70,8 @@ typedef struct {
     void *stream;          /* hipStream_t to run on, or NULL */
     int32_t lanes_per_arc; /* 0: automatic; else a power of two 1..1024 (tuning) */
     int32_t vec_per_lane;  /* 0: automatic; else 1, 2, 4 or 8 (tuning) */
+    int32_t graph_sweeps;  /* passes per captured HIP graph in pdr_sweep: 0 = 32,
+                              < 0 = launch every kernel directly */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */
@@ -122,6 +124,21 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
  * Errors: PDR_ERR_INVALID for max_sweeps < 0; PDR_ERR_DEVICE.
  */
 pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_target);
+
+/*
+ * Run passes until the objective z (evaluated in FP64 from the stored flows)
+ * is <= z_target, or until max_sweeps passes in total (synchronizes).
+ * In PDR_FP32_BULK the passes run in FP32 until the objective stalls -- the
+ * smallest z of the last `window` evaluations is not below (1 - 1e-3) times
+ * the smallest z before them -- then the flows are widened to FP64 exactly
+ * (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
+ * In PDR_FP64 it is pdr_sweep with the z_target stop test.
+ * sweeps_fp32 / sweeps_fp64 (may be NULL) receive the passes run in each
+ * precision. Errors: PDR_ERR_INVALID for z_target <= 0, max_sweeps < 0 or
+ * window < 1; PDR_ERR_NUMERIC for a non-finite objective; PDR_ERR_DEVICE.
+ */
+pdr_status pdr_solve(pdr_ctx *ctx, double z_target, int64_t max_sweeps, int64_t window,
+                     int64_t *sweeps_fp32, int64_t *sweeps_fp64);
 
 /* Compute the FP64 residual report of the current flows (synchronizes).
  * Returns PDR_ERR_NUMERIC (and fills *out) if z is not finite. */

@@ -4,6 +4,12 @@ Thin ctypes binding over ``libpdr.so`` (the C ABI of ``include/pdr.h``). Every
 step of a sweep runs in the library's HIP kernels; this module only marshals
 arguments. It raises if the library is missing -- there is no CPU fallback.
 
+To pass torch device tensors or torch streams, import torch before the first
+use of this module: the library then binds to torch's HIP runtime (both carry
+the same soname), so pointers and streams are shared. Loaded without torch it
+uses the system ROCm runtime, and a torch imported afterwards would start a
+second runtime that does not see the device.
+
 Method: Liu, "A Localized Method for Multicommodity Flow Problem" (arXiv 2108.07549):
 heights from excess (Section 3.1), the exact edge subproblem (PDR-ESO,
 Section 4, Algorithms 1-2) and the adaptive-gradient update (PDR-AGD,
@@ -25,7 +31,7 @@ VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
 STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVICE",
           4: "PDR_ERR_STATE", 5: "PDR_ERR_NUMERIC"}
 
-EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_residual", "pdr_flows",
+EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
            "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_z_log",
            "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_tiling", "pdr_destroy",
            "pdr_last_error"]
@@ -46,7 +52,8 @@ class AgdParams(C.Structure):
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("agd", AgdParams),
                 ("z_feasible_tol", C.c_double), ("stream", C.c_void_p),
-                ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32)]
+                ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32),
+                ("graph_sweeps", C.c_int32)]
 
 
 class Residual(C.Structure):
@@ -77,6 +84,7 @@ def lib():
         L.pdr_default_options.restype = None
         L.pdr_init.argtypes = [C.POINTER(P), i32, i32, P, P, P, i32, P, P, P, C.POINTER(Options)]
         L.pdr_sweep.argtypes = [P, i64, dbl, dbl]
+        L.pdr_solve.argtypes = [P, dbl, i64, i64, C.POINTER(i64), C.POINTER(i64)]
         L.pdr_residual.argtypes = [P, C.POINTER(Residual)]
         L.pdr_flows.argtypes = [P, P]
         L.pdr_flows_device.argtypes = [P, P, i32]
@@ -98,6 +106,15 @@ def lib():
     return _lib
 
 
+def device_synchronize():
+    """hipDeviceSynchronize on the HIP runtime the library is bound to."""
+    lib()
+    hip = C.CDLL("libamdhip64.so.7")  # already loaded with the library: the same runtime
+    st = hip.hipDeviceSynchronize()
+    if st != 0:
+        raise RuntimeError(f"hipDeviceSynchronize failed with error {st}")
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
@@ -111,7 +128,7 @@ def _stream_handle(stream):
 
 
 def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, vec_per_lane=0,
-                    z_feasible_tol=1e-8, agd=None) -> Options:
+                    z_feasible_tol=1e-8, agd=None, graph_sweeps=0) -> Options:
     opt = Options()
     lib().pdr_default_options(C.byref(opt))
     opt.method = int(method)
@@ -120,6 +137,7 @@ def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, ve
     opt.lanes_per_arc = int(lanes_per_arc)
     opt.vec_per_lane = int(vec_per_lane)
     opt.z_feasible_tol = float(z_feasible_tol)
+    opt.graph_sweeps = int(graph_sweeps)
     if agd:
         for k, v in agd.items():
             setattr(opt.agd, k, v)
@@ -130,7 +148,7 @@ class Context:
     """One PDR instance resident on the GPU (wraps pdr_init ... pdr_destroy)."""
 
     def __init__(self, n, row_ptr, col, u, s, t, d, method=ESO, precision=FP64, stream=None,
-                 lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None):
+                 lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None, graph_sweeps=0):
         L = lib()
         self._h = C.c_void_p()
         self._keep = [np.ascontiguousarray(row_ptr, np.int64), np.ascontiguousarray(col, np.int32),
@@ -139,7 +157,7 @@ class Context:
         rp, cl, uu, ss, tt, dd = self._keep
         self.n, self.m, self.K = int(n), int(cl.shape[0]), int(ss.shape[0])
         opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane,
-                              z_feasible_tol, agd)
+                              z_feasible_tol, agd, graph_sweeps)
         st = L.pdr_init(C.byref(self._h), int(n), self.m, _ptr(rp), _ptr(cl), _ptr(uu), self.K,
                         _ptr(ss), _ptr(tt), _ptr(dd), C.byref(opt))
         if st != 0:
@@ -162,6 +180,14 @@ class Context:
     # -- ABI mirror
     def sweep(self, max_sweeps: int, eps_obj: float = 0.0, z_target: float = 0.0):
         self._check(lib().pdr_sweep(self._h, int(max_sweeps), float(eps_obj), float(z_target)))
+
+    def solve(self, z_target: float, max_sweeps: int, window: int = 256):
+        """Run to z <= z_target; FP32-bulk contexts switch to the FP64 polish when
+        the objective stalls. Returns (passes in FP32, passes in FP64)."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().pdr_solve(self._h, float(z_target), int(max_sweeps), int(window),
+                                    C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def residual(self) -> dict:
         r = Residual()

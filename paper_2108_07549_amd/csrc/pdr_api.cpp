@@ -35,6 +35,9 @@ struct pdr_ctx {
     bool own_stream = false;
     int32_t req_lanes = 0, req_nv = 0;
     Tiling tiling{1, 1};
+    int32_t graph_sweeps = 32;             // passes per captured graph; 0 = no graphs
+    hipStream_t cap_stream = nullptr;      // private stream used only for capture
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
     std::string err;
 
@@ -213,6 +216,53 @@ pdr_status push_ctrl(pdr_ctx *c)
     return PDR_OK;
 }
 
+pdr::AgdParams agd_params(const pdr_ctx *c)
+{
+    return pdr::AgdParams{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
+                          c->agd.inc_period};
+}
+
+// Enqueue `count` passes (height, objective + stop test, arc update) on st.
+hipError_t enqueue_passes(pdr_ctx *c, int64_t count, hipStream_t st)
+{
+    const bool fp64 = c->precision == PDR_FP64;
+    void *f = cur_f(c);
+    void *h = cur_h(c);
+    const int64_t nz = pdr::height_blocks(c->g, fp64 ? 8 : 4);
+    const pdr::AgdParams prm = agd_params(c);
+    for (int64_t q = 0; q < count; ++q) {
+        hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, st);
+        if (e == hipSuccess) e = pdr::launch_reduce(c->g, c->zpart, nz, c->Fsum, c->ctrl, c->zlog, st);
+        if (e == hipSuccess)
+            e = c->method == PDR_ESO
+                    ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, st)
+                    : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm, c->ctrl, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The graph of graph_sweeps passes for the current precision (kernels only;
+// the kernels read the stop flag, so passes after a stop do nothing).
+pdr_status sweep_graph(pdr_ctx *c, hipGraphExec_t *out)
+{
+    hipGraphExec_t &ge = c->gexec[c->precision];
+    if (!ge) {
+        if (!c->cap_stream) PDR_CHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        PDR_CHECK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_passes(c, c->graph_sweeps, c->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+        PDR_CHECK(c, e);
+        PDR_CHECK(c, e2);
+        e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PDR_CHECK(c, e);
+    }
+    *out = ge;
+    return PDR_OK;
+}
+
 void free_all(pdr_ctx *c)
 {
     // teardown: failures here cannot be reported and leave nothing to undo
@@ -223,6 +273,10 @@ void free_all(pdr_ctx *c)
     if (c->h_res) (void)hipHostFree(c->h_res);
     c->h_ctrl = nullptr;
     c->h_res = nullptr;
+    for (auto &ge : c->gexec)
+        if (ge) (void)hipGraphExecDestroy(ge);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
 }
@@ -250,6 +304,7 @@ void pdr_default_options(pdr_options *opt)
     opt->stream = nullptr;
     opt->lanes_per_arc = 0;
     opt->vec_per_lane = 0;
+    opt->graph_sweeps = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -340,6 +395,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->z_feasible_tol = opt.z_feasible_tol;
     c->req_lanes = opt.lanes_per_arc;
     c->req_nv = opt.vec_per_lane;
+    c->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
         if (st != PDR_OK) return init_fail(c, st, out);
@@ -487,25 +543,26 @@ pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_ta
     if (max_sweeps < 0) return fail(c, PDR_ERR_INVALID, "max_sweeps must be >= 0");
     if (std::isnan(eps_obj) || std::isnan(z_target))
         return fail(c, PDR_ERR_INVALID, "eps_obj and z_target must not be NaN");
-    const bool fp64 = c->precision == PDR_FP64;
-    void *f = cur_f(c);
-    void *h = cur_h(c);
     PDR_CHECK(c, pdr::launch_begin(c->ctrl, eps_obj, z_target, c->stream));
     const bool poll = eps_obj > 0.0 || z_target > 0.0;
-    int64_t batch = 16;
-    int64_t since = 0;
-    const pdr::AgdParams prm{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
-                             c->agd.inc_period};
-    for (int64_t s = 0; s < max_sweeps; ++s) {
-        PDR_CHECK(c, pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, c->stream));
-        PDR_CHECK(c, pdr::launch_reduce(c->g, c->zpart, pdr::height_blocks(c->g, fp64 ? 8 : 4),
-                                        c->Fsum, c->ctrl, c->zlog, c->stream));
-        if (c->method == PDR_ESO)
-            PDR_CHECK(c, pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream));
-        else
-            PDR_CHECK(c, pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
-                                         c->ctrl, c->stream));
-        if (poll && ++since >= batch && s + 1 < max_sweeps) {
+    const int64_t G = c->graph_sweeps;
+    hipGraphExec_t ge = nullptr;
+    if (G > 0 && max_sweeps >= G) {
+        st = sweep_graph(c, &ge);
+        if (st != PDR_OK) return st;
+    }
+    int64_t batch = 16, since = 0, s = 0;
+    while (s < max_sweeps) {
+        if (ge && max_sweeps - s >= G) {
+            PDR_CHECK(c, hipGraphLaunch(ge, c->stream));
+            s += G;
+            since += G;
+        } else {
+            PDR_CHECK(c, enqueue_passes(c, 1, c->stream));
+            s += 1;
+            since += 1;
+        }
+        if (poll && since >= batch && s < max_sweeps) {
             since = 0;
             if (batch < 1024) batch *= 2;
             st = sync_ctrl(c);
@@ -513,6 +570,47 @@ pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_ta
             if (c->h_ctrl->stopped) break;
         }
     }
+    return PDR_OK;
+}
+
+pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t window,
+                     int64_t *sweeps_fp32, int64_t *sweeps_fp64)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (!(z_target > 0.0) || max_sweeps < 0 || window < 1)
+        return fail(c, PDR_ERR_INVALID, "need z_target > 0, max_sweeps >= 0, window >= 1");
+    int64_t n32 = 0, n64 = 0, total = 0;
+    double best_before = std::numeric_limits<double>::infinity();
+    std::vector<double> zl;
+    while (total < max_sweeps) {
+        st = sync_ctrl(c);
+        if (st != PDR_OK) return st;
+        const int64_t t0 = c->h_ctrl->t, ev0 = c->h_ctrl->evals;
+        const int64_t chunk = std::min(window, max_sweeps - total);
+        st = pdr_sweep(c, chunk, 0.0, z_target);
+        if (st != PDR_OK) return st;
+        st = sync_ctrl(c);
+        if (st != PDR_OK) return st;
+        const int64_t ran = c->h_ctrl->t - t0, nev = c->h_ctrl->evals - ev0;
+        (c->precision == PDR_FP64 ? n64 : n32) += ran;
+        total += ran;
+        if (c->h_ctrl->numeric) return fail(c, PDR_ERR_NUMERIC, "the objective is not finite");
+        if (c->h_ctrl->stopped || ran == 0) break;
+        if (c->precision == PDR_FP32_BULK && nev > 0) {
+            zl.resize((size_t)nev);
+            st = pdr_z_log(c, ev0, nev, zl.data());
+            if (st != PDR_OK) return st;
+            const double cur = *std::min_element(zl.begin(), zl.end());
+            if (!(cur < (1.0 - 1e-3) * best_before)) {
+                st = pdr_set_precision(c, PDR_FP64);
+                if (st != PDR_OK) return st;
+            }
+            best_before = std::min(best_before, cur);
+        }
+    }
+    if (sweeps_fp32) *sweeps_fp32 = n32;
+    if (sweeps_fp64) *sweeps_fp64 = n64;
     return PDR_OK;
 }
 
@@ -524,8 +622,7 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
     const bool fp64 = c->precision == PDR_FP64;
     void *f = cur_f(c);
     void *h = cur_h(c);
-    const pdr::AgdParams prm{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
-                             c->agd.inc_period};
+    const pdr::AgdParams prm = agd_params(c);
     constexpr int B = 64;  // sweeps per batch of events
     hipEvent_t ev[B][4];
     for (int q = 0; q < B; ++q)

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
 // PDR-AGD arc update (Algorithm 3): phi_k = h_ik - h_jk - psi,
 // df_k = max(-f_k, beta phi_k); the step is kept iff the exact change of the
 // edge subproblem objective (Expression 13, optimal slack),
-// dz = 1/2[(F + sum df - u)_+^2 - psi^2] + sum_k (df_k^2 - df_k (h_ik - h_jk)),
+// dz = 1/2[(F + sum df - u)_+^2 - psi^2] + sum_k df_k (df_k - (h_ik - h_jk)),
 // is <= 0; otherwise beta <- max(beta_min, alpha_dec beta). Every inc_period
 // iterations beta <- min(beta_max, alpha_inc beta).
 template <typename T, int L, int NV>
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
                 const double step = b * ((double)gg - psi);
                 const double df = step > -fx ? step : -fx;
                 red[0] += df;
-                red[1] += df * df - df * (double)gg;
+                red[1] += df * (df - (double)gg);
                 red[2] += (double)(T)(fx + df);
             }
         } else {
@@ -444,9 +444,15 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
         }
     }
     group_sum<L, 3>(red, lds, phase);
-    const double over = F + red[0] - u;
-    const double npsi = over > 0.0 ? over : 0.0;
-    const double dz = 0.5 * (npsi * npsi - psi * psi) + red[1];
+    // congestion part 1/2[(F + S - u)_+^2 - (F - u)_+^2]; factored as
+    // S (F - u + S/2) when over capacity before and after the step, so that a
+    // small step is not lost in the difference of two large squares
+    const double before = F - u, after = F + red[0] - u;
+    const double dcong = (before > 0.0 && after > 0.0)
+                             ? red[0] * (before + 0.5 * red[0])
+                             : 0.5 * ((after > 0.0 ? after * after : 0.0) -
+                                      (before > 0.0 ? before * before : 0.0));
+    const double dz = dcong + red[1];
     const bool accept = dz <= 0.0;
     if (accept) {
         T *fo = f + e * Kp;
