@@ -246,3 +246,29 @@ def congestion_bracket_fw(inst, iters: int = 60, kappa: float = 40.0, verbose: b
         if time.time() - t0 > time_limit:
             break
     return dict(mu_hi=mu_hi, mu_lo=mu_lo, iters=it, columns=0, seconds=time.time() - t0)
+
+
+def grid_cut_bound(inst, a: int, b: int) -> float:
+    """Lower bound on the minimum congestion of an a x b grid instance from its
+    straight cuts: every vertical or horizontal line splits the grid, and all
+    demand from one side to the other must cross the arcs of the cut in that
+    direction, so mu* >= demand / capacity for each cut and direction."""
+    tails = inst.tails().astype(np.int64)
+    heads = inst.col.astype(np.int64)
+    rt, ct = np.divmod(tails, b)
+    rh, ch = np.divmod(heads, b)
+    rs, cs = np.divmod(inst.s.astype(np.int64), b)
+    rk, ck = np.divmod(inst.t.astype(np.int64), b)
+    best = 0.0
+    for (pt, ph, ps, pk, size) in ((ct, ch, cs, ck, b), (rt, rh, rs, rk, a)):
+        for c in range(size - 1):
+            for sgn in (1, -1):
+                side_t = (pt <= c) if sgn > 0 else (pt > c)
+                side_h = (ph > c) if sgn > 0 else (ph <= c)
+                cap = float(inst.u[side_t & side_h].sum())
+                src = (ps <= c) if sgn > 0 else (ps > c)
+                dst = (pk > c) if sgn > 0 else (pk <= c)
+                dem = float(inst.d[src & dst].sum())
+                if cap > 0:
+                    best = max(best, dem / cap)
+    return best

@@ -69,9 +69,13 @@ typedef struct {
     double z_feasible_tol; /* verdict FEASIBLE needs z <= this (default 1e-8) */
     void *stream;          /* hipStream_t to run on, or NULL */
     int32_t lanes_per_arc; /* 0: automatic; else a power of two 1..1024 (tuning) */
-    int32_t vec_per_lane;  /* 0: automatic; else 1, 2, 4 or 8 (tuning) */
+    int32_t vec_per_lane;  /* 0: automatic; else a count the library instantiates for
+                              that lane count: 1, 2, 4, 8 for all; 10, 12, 16, 20
+                              for 128 and 256; 3, 5, 6 for 256 and more (tuning) */
     int32_t graph_sweeps;  /* passes per captured HIP graph in pdr_sweep: 0 = 32,
                               < 0 = launch every kernel directly */
+    int32_t height_chunk;  /* 16-byte vectors per commodity chunk in the height
+                              kernel: 0 = automatic, else a power of two 1..256 */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */
@@ -176,9 +180,17 @@ pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, int6
 
 /* Measurement: run `sweeps` passes like pdr_sweep without a stop test,
  * recording HIP events around every kernel on the context stream. On return
- * (synchronized) kernel_ms[0], [1], [2] hold the summed device time in
- * milliseconds of the height, objective and arc-update kernels. */
+ * (synchronized) kernel_ms[0] and kernel_ms[1] hold the summed device time in
+ * milliseconds of the height kernel (which also evaluates the objective and
+ * the stop test) and of the arc-update kernel. */
 pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
+
+/* Measurement: the HBM bandwidth of a plain copy on the current device.
+ * Copies `bytes` (rounded down to 16) between two freshly allocated device
+ * buffers `iters` times with a 16-byte-vector grid-stride kernel (k_copy) and
+ * writes the mean read+write bandwidth in GB/s (2 * bytes per copy / time)
+ * to *gbps. The buffers are freed before return. Context-free. */
+pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps);
 
 /* Query the automatic tiling: lanes per arc and vectors per lane of the arc
  * kernels, and the padded commodity stride Kp. */

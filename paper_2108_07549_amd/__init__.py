@@ -33,8 +33,8 @@ STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVIC
 
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
            "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_z_log",
-           "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_tiling", "pdr_destroy",
-           "pdr_last_error"]
+           "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
+           "pdr_tiling", "pdr_destroy", "pdr_last_error"]
 
 
 class PdrError(RuntimeError):
@@ -53,7 +53,7 @@ class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("agd", AgdParams),
                 ("z_feasible_tol", C.c_double), ("stream", C.c_void_p),
                 ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32),
-                ("graph_sweeps", C.c_int32)]
+                ("graph_sweeps", C.c_int32), ("height_chunk", C.c_int32)]
 
 
 class Residual(C.Structure):
@@ -94,6 +94,7 @@ def lib():
         L.pdr_set_precision.argtypes = [P, i32]
         L.pdr_set_state.argtypes = [P, P, P, i64, dbl]
         L.pdr_profile_sweeps.argtypes = [P, i64, P]
+        L.pdr_measure_copy.argtypes = [i64, i32, P]
         L.pdr_tiling.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.pdr_destroy.argtypes = [P]
         L.pdr_destroy.restype = None
@@ -104,6 +105,15 @@ def lib():
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+def measure_copy(nbytes: int = 4 << 30, iters: int = 10) -> float:
+    """HBM bandwidth (GB/s, read + write) of a plain 16-byte copy kernel."""
+    out = np.zeros(1, np.float64)
+    st = lib().pdr_measure_copy(int(nbytes), int(iters), _ptr(out))
+    if st != 0:
+        raise PdrError(st, lib().pdr_last_error(None).decode())
+    return float(out[0])
 
 
 def device_synchronize():
@@ -128,7 +138,7 @@ def _stream_handle(stream):
 
 
 def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, vec_per_lane=0,
-                    z_feasible_tol=1e-8, agd=None, graph_sweeps=0) -> Options:
+                    z_feasible_tol=1e-8, agd=None, graph_sweeps=0, height_chunk=0) -> Options:
     opt = Options()
     lib().pdr_default_options(C.byref(opt))
     opt.method = int(method)
@@ -138,6 +148,7 @@ def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, ve
     opt.vec_per_lane = int(vec_per_lane)
     opt.z_feasible_tol = float(z_feasible_tol)
     opt.graph_sweeps = int(graph_sweeps)
+    opt.height_chunk = int(height_chunk)
     if agd:
         for k, v in agd.items():
             setattr(opt.agd, k, v)
@@ -148,7 +159,8 @@ class Context:
     """One PDR instance resident on the GPU (wraps pdr_init ... pdr_destroy)."""
 
     def __init__(self, n, row_ptr, col, u, s, t, d, method=ESO, precision=FP64, stream=None,
-                 lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None, graph_sweeps=0):
+                 lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None, graph_sweeps=0,
+                 height_chunk=0):
         L = lib()
         self._h = C.c_void_p()
         self._keep = [np.ascontiguousarray(row_ptr, np.int64), np.ascontiguousarray(col, np.int32),
@@ -157,7 +169,7 @@ class Context:
         rp, cl, uu, ss, tt, dd = self._keep
         self.n, self.m, self.K = int(n), int(cl.shape[0]), int(ss.shape[0])
         opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane,
-                              z_feasible_tol, agd, graph_sweeps)
+                              z_feasible_tol, agd, graph_sweeps, height_chunk)
         st = L.pdr_init(C.byref(self._h), int(n), self.m, _ptr(rp), _ptr(cl), _ptr(uu), self.K,
                         _ptr(ss), _ptr(tt), _ptr(dd), C.byref(opt))
         if st != 0:
@@ -235,8 +247,8 @@ class Context:
 
     def profile_sweeps(self, sweeps: int) -> np.ndarray:
         """Run sweeps without a stop test; returns summed device ms of the
-        (height, objective, arc) kernels measured with HIP events."""
-        out = np.zeros(3, np.float64)
+        (height + objective, arc) kernels measured with HIP events."""
+        out = np.zeros(2, np.float64)
         self._check(lib().pdr_profile_sweeps(self._h, int(sweeps), _ptr(out)))
         return out
 

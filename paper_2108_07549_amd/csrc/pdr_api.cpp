@@ -20,7 +20,10 @@ using pdr::Tiling;
 namespace {
 thread_local std::string g_init_error;
 constexpr int kMaxLanes = 1024;
-constexpr int kMaxNv = 8;
+constexpr int kMaxNv = 20;
+// Vectors per commodity chunk in the height kernel: small enough that the
+// rows read by a window of neighbouring vertices stay in L2.
+constexpr int kHeightChunkAuto = 64;
 }  // namespace
 
 struct pdr_ctx {
@@ -36,6 +39,7 @@ struct pdr_ctx {
     int32_t req_lanes = 0, req_nv = 0;
     Tiling tiling{1, 1};
     int32_t graph_sweeps = 32;             // passes per captured graph; 0 = no graphs
+    int32_t req_height_chunk = 0;          // 0 = automatic
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
@@ -118,9 +122,18 @@ int vec_of(int32_t precision) { return precision == PDR_FP64 ? 2 : 4; }
 Tiling auto_tiling(int32_t Kp, int32_t precision)
 {
     const int64_t nvec = Kp / vec_of(precision);
-    int L = pow2ceil((nvec + 3) / 4);
+    // about five register vectors per lane: long rows get many lanes, and
+    // the blocks stay small enough that several arcs share a CU
+    int L = pow2ceil((nvec + 4) / 5);
     if (L > kMaxLanes) L = kMaxLanes;
-    int nv = pow2ceil((nvec + L - 1) / L);
+    const int need = (int)((nvec + L - 1) / L);
+    // the fewest register vectors per lane that cover the row
+    int nv = pow2ceil(need);
+    for (int cand = need; cand <= nv; ++cand)
+        if (pdr::tiling_supported(L, cand)) {
+            nv = cand;
+            break;
+        }
     if (nv < 1) nv = 1;
     return Tiling{L, nv};
 }
@@ -168,6 +181,15 @@ bool usable(pdr_ctx *c, pdr_status *st)
         return false;
     }
     return true;
+}
+
+// Vectors per commodity chunk of the height kernel: a whole 256-thread block
+// per (vertex, chunk) when rows are long, several vertices per block otherwise.
+void set_height_chunk(pdr_ctx *c)
+{
+    const int64_t nvec = c->Kp / vec_of(c->precision);
+    const int cap = c->req_height_chunk > 0 ? c->req_height_chunk : kHeightChunkAuto;
+    c->g.height_cv = std::min<int>(cap, pow2ceil(nvec));
 }
 
 void *cur_f(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->f64 : (void *)c->f32; }
@@ -228,11 +250,9 @@ hipError_t enqueue_passes(pdr_ctx *c, int64_t count, hipStream_t st)
     const bool fp64 = c->precision == PDR_FP64;
     void *f = cur_f(c);
     void *h = cur_h(c);
-    const int64_t nz = pdr::height_blocks(c->g, fp64 ? 8 : 4);
     const pdr::AgdParams prm = agd_params(c);
     for (int64_t q = 0; q < count; ++q) {
-        hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, st);
-        if (e == hipSuccess) e = pdr::launch_reduce(c->g, c->zpart, nz, c->Fsum, c->ctrl, c->zlog, st);
+        hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog, st);
         if (e == hipSuccess)
             e = c->method == PDR_ESO
                     ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, st)
@@ -305,6 +325,7 @@ void pdr_default_options(pdr_options *opt)
     opt->lanes_per_arc = 0;
     opt->vec_per_lane = 0;
     opt->graph_sweeps = 0;
+    opt->height_chunk = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -382,6 +403,9 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     if (!(opt.z_feasible_tol >= 0) || !std::isfinite(opt.z_feasible_tol))
         return invalid("z_feasible_tol must be finite and >= 0");
     if (opt.lanes_per_arc < 0 || opt.vec_per_lane < 0) return invalid("negative tiling request");
+    if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
+        (opt.height_chunk & (opt.height_chunk - 1)) != 0)
+        return invalid("height_chunk must be 0 or a power of two up to 256");
 
     pdr_ctx *c = new pdr_ctx();
     c->n = n;
@@ -396,6 +420,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->req_lanes = opt.lanes_per_arc;
     c->req_nv = opt.vec_per_lane;
     c->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
+    c->req_height_chunk = opt.height_chunk;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
         if (st != PDR_OK) return init_fail(c, st, out);
@@ -422,7 +447,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
         const double mK = (double)m * c->Kp, nK = (double)n * c->Kp;
         double need = mK * w + nK * w + nK * 8.0 * (c->precision == PDR_FP64 ? 0.0 : 1.0) +
                       8.0 * (6.0 * m + 4.0 * n + 4.0 * K) + 8.0 * (double)pdr::kZLogCap +
-                      16.0 * (double)pdr::height_blocks(DevGraph{n, m, K, c->Kp}, 8);
+                      16.0 * (double)pdr::kHeightBlocksMax;
         size_t free_b = 0, total_b = 0;
         e = hipMemGetInfo(&free_b, &total_b);
         if (e != hipSuccess) {
@@ -491,9 +516,11 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     PDR_UP(c->d_t, t, K);
     PDR_UP(c->d_d, d, K);
 #undef PDR_UP
-    c->g = DevGraph{n,         m,          K,           c->Kp,         c->d_row_ptr, c->d_tails,
-                    c->d_heads, c->d_in_ptr, c->d_in_idx, c->d_deg,     c->d_inj_ptr, c->d_inj_k,
-                    c->d_inj_val, c->d_u,   c->d_s,      c->d_t,        c->d_d};
+    c->g = DevGraph{n,           m,         K,           c->Kp,        0,
+                    c->d_row_ptr, c->d_tails, c->d_heads, c->d_in_ptr, c->d_in_idx,
+                    c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
+                    c->d_s,       c->d_t,     c->d_d};
+    set_height_chunk(c);
 
     pdr_status st = ensure_buffers(c, c->precision);
     if (st != PDR_OK) return init_fail(c, st, out);
@@ -505,7 +532,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     } while (0)
     PDR_AL(c->Fsum, m);
     PDR_AL(c->beta, m);
-    PDR_AL(c->zpart, c->nzpart);
+    PDR_AL(c->zpart, 2 * c->nzpart);
     PDR_AL(c->maxpart, c->nzpart);
     PDR_AL(c->arcpart, 3 * (size_t)m);
     PDR_AL(c->resout, 8);
@@ -624,41 +651,39 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
     void *h = cur_h(c);
     const pdr::AgdParams prm = agd_params(c);
     constexpr int B = 64;  // sweeps per batch of events
-    hipEvent_t ev[B][4];
+    hipEvent_t ev[B][3];
     for (int q = 0; q < B; ++q)
-        for (int r = 0; r < 4; ++r) PDR_CHECK(c, hipEventCreate(&ev[q][r]));
-    double tot[3] = {0.0, 0.0, 0.0};
+        for (int r = 0; r < 3; ++r) PDR_CHECK(c, hipEventCreate(&ev[q][r]));
+    double tot[2] = {0.0, 0.0};
     hipError_t err = pdr::launch_begin(c->ctrl, 0.0, 0.0, c->stream);
     for (int64_t s0 = 0; s0 < sweeps && err == hipSuccess; s0 += B) {
         const int nb = (int)std::min<int64_t>(B, sweeps - s0);
         for (int q = 0; q < nb && err == hipSuccess; ++q) {
             err = hipEventRecord(ev[q][0], c->stream);
             if (err == hipSuccess)
-                err = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->ctrl, true, c->stream);
+                err = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog,
+                                         c->stream);
             if (err == hipSuccess) err = hipEventRecord(ev[q][1], c->stream);
-            if (err == hipSuccess)
-                err = pdr::launch_reduce(c->g, c->zpart, pdr::height_blocks(c->g, fp64 ? 8 : 4),
-                                         c->Fsum, c->ctrl, c->zlog, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(ev[q][2], c->stream);
             if (err == hipSuccess)
                 err = c->method == PDR_ESO
                           ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream)
                           : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
                                             c->ctrl, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(ev[q][3], c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[q][2], c->stream);
         }
-        if (err == hipSuccess) err = hipEventSynchronize(ev[nb - 1][3]);
+        if (err == hipSuccess) err = hipEventSynchronize(ev[nb - 1][2]);
         for (int q = 0; q < nb && err == hipSuccess; ++q)
-            for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+            for (int r = 0; r < 2 && err == hipSuccess; ++r) {
                 float ms = 0.0f;
                 err = hipEventElapsedTime(&ms, ev[q][r], ev[q][r + 1]);
                 tot[r] += ms;
             }
     }
     for (int q = 0; q < B; ++q)
-        for (int r = 0; r < 4; ++r) (void)hipEventDestroy(ev[q][r]);
+        for (int r = 0; r < 3; ++r) (void)hipEventDestroy(ev[q][r]);
     PDR_CHECK(c, err);
-    for (int r = 0; r < 3; ++r) kernel_ms[r] = tot[r];
+    kernel_ms[0] = tot[0];
+    kernel_ms[1] = tot[1];
     return PDR_OK;
 }
 
@@ -801,6 +826,7 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
         PDR_CHECK(c, pdr::launch_convert(c->f64, true, c->f32, false, mK, c->stream));
     c->precision = precision;
     c->tiling = tl;
+    set_height_chunk(c);
     PDR_CHECK(c, pdr::launch_rowsum(c->g, precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
                                     c->stream));
     PDR_CHECK(c, hipStreamSynchronize(c->stream));
@@ -855,6 +881,48 @@ pdr_status pdr_tiling(const pdr_ctx *c, int32_t *lanes_per_arc, int32_t *vec_per
     if (lanes_per_arc) *lanes_per_arc = c->tiling.lanes;
     if (vec_per_lane) *vec_per_lane = c->tiling.nv;
     if (Kp) *Kp = c->Kp;
+    return PDR_OK;
+}
+
+pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
+{
+    if (bytes < 16 || iters < 1 || !gbps) {
+        g_init_error = "pdr_measure_copy: need bytes >= 16, iters >= 1, gbps";
+        return PDR_ERR_INVALID;
+    }
+    const int64_t n16 = bytes / 16;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, (size_t)n16 * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, (size_t)n16 * 16);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, (size_t)n16 * 16, st);
+    if (e == hipSuccess) e = pdr::launch_copy(a, b, n16, st);  // warm up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int q = 0; q < iters && e == hipSuccess; ++q)
+        e = pdr::launch_copy(q % 2 ? b : a, q % 2 ? a : b, n16, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) *gbps = 2.0 * (double)n16 * 16.0 * iters / (ms * 1e-3) / 1e9;
+    const hipError_t err = e;
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (st) (void)hipStreamDestroy(st);
+    if (b) (void)hipFree(b);
+    if (a) (void)hipFree(a);
+    if (err == hipErrorOutOfMemory) {
+        g_init_error = "pdr_measure_copy: out of device memory";
+        return PDR_ERR_OOM;
+    }
+    if (err != hipSuccess) {
+        g_init_error = std::string("pdr_measure_copy: ") + hipGetErrorString(err);
+        return PDR_ERR_DEVICE;
+    }
     return PDR_OK;
 }
 

@@ -22,10 +22,14 @@ struct Ctrl {
 };
 
 constexpr int64_t kZLogCap = int64_t(1) << 20;
+// The height kernel is grid-stride with at most this many blocks (8 per CU),
+// which also bounds the number of objective partials.
+constexpr int64_t kHeightBlocksMax = 2048;
 
 // Graph and instance arrays in device memory.
 struct DevGraph {
     int32_t n, m, K, Kp;
+    int32_t height_cv;       // vectors per commodity chunk in the height kernel
     const int32_t *row_ptr;  // n+1: out-arcs of i are [row_ptr[i], row_ptr[i+1])
     const int32_t *tails;    // m
     const int32_t *heads;    // m
@@ -57,12 +61,11 @@ int64_t height_blocks(const DevGraph &g, int elem_bytes);
 
 // Launchers; each returns the launch status.
 hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st);
+// Heights of the current flows, then the objective and stop test (two kernels).
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
-                         const Ctrl *ctrl, bool check_stop, hipStream_t st);
+                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st);
 hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, double *h64,
                                double *zpart, double *maxpart, hipStream_t st);
-hipError_t launch_reduce(const DevGraph &g, const double *zpart, int64_t nzpart,
-                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st);
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
                       double *Fsum, const Ctrl *ctrl, hipStream_t st);
 hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
@@ -75,6 +78,7 @@ hipError_t launch_resid(const DevGraph &g, bool fp64, const void *f, const doubl
                         const double *Fsum, const double *zpart, int64_t nzpart,
                         const double *maxpart, double *arcpart, double *out,
                         hipStream_t st);
+hipError_t launch_copy(const void *src, void *dst, int64_t count16, hipStream_t st);
 hipError_t launch_convert(const void *src, bool src_fp64, void *dst, bool dst_fp64,
                           int64_t count, hipStream_t st);
 // Unpadded copy of flows: dst[e*K + k] = f[e*Kp + k].

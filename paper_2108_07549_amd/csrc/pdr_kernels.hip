@@ -7,11 +7,11 @@
 // Padded entries (k >= K) are zero and stay zero under both arc updates.
 //
 // A sweep is three launches on one stream:
-//   k_height  excess -> height (Expressions 2-4), one thread per 16-byte
+//   k_height  excess -> height (Expressions 2-4), one work item per 16-byte
 //             vector of a vertex row; FP64 accumulation; per-block partials
-//             of sum Delta * h for the objective.
-//   k_reduce  objective z (Algorithm 1) from those partials and Fsum; z log;
-//             the stop test; the iteration counter. One block.
+//             of sum Delta * h.
+//   k_reduce  objective z (Algorithm 1) from those partials and Fsum, the z
+//             log, the stop test and the iteration counter (one block).
 //   k_eso / k_agd  every arc in parallel (Expression 14 / Algorithm 3). A
 //             group of L lanes owns one arc and holds its row in registers;
 //             per-arc sums are FP64 group reductions with a fixed tree, so
@@ -137,27 +137,98 @@ __global__ void k_begin(Ctrl *ctrl, double eps_obj, double z_target)
     }
 }
 
+// ----------------------------------------------------------------- objective + stop test
+// One block: z = 1/2 sum of the height kernel's per-block partials of
+// Delta * h and of max(0, Fsum_e - u_e)^2 (Algorithm 1), the z log, the stop
+// test of Algorithm 1 (|z - z_prev| < eps_obj) or z <= z_target, and the
+// iteration counter. The partials come two per height block, so this block
+// reads at most 2 * kHeightBlocksMax values.
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int nz,
+                                                 Ctrl *__restrict__ ctrl,
+                                                 double *__restrict__ zlog)
+{
+    if (ctrl->stopped) return;
+    __shared__ double sh[2][16];
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < nz; q += 1024) {
+        a += zpart[q];
+        b += zpart[nz + q];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0.0, B = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            A += sh[0][q];
+            B += sh[1][q];
+        }
+        const double zh = 0.5 * A, zp = 0.5 * B, z = zp + zh;
+        const int64_t ev = ctrl->evals;
+        zlog[ev & (kZLogCap - 1)] = z;
+        ctrl->evals = ev + 1;
+        ctrl->z = z;
+        ctrl->z_psi = zp;
+        ctrl->z_h = zh;
+        const bool fin = isfinite(z);
+        const bool stop = !fin || (ctrl->eps_obj > 0.0 && fabs(z - ctrl->z_prev) < ctrl->eps_obj) ||
+                          (ctrl->z_target > 0.0 && z <= ctrl->z_target);
+        if (!fin) ctrl->numeric = 1;
+        if (stop) {
+            ctrl->stopped = 1;
+        } else {
+            ctrl->z_prev = z;
+            ctrl->t_pass = ctrl->t;
+            ctrl->t = ctrl->t + 1;
+        }
+    }
+}
+
 // ----------------------------------------------------------------- excess -> height
-// Thread (i, q) computes Delta_ik = sum_in f - sum_out f + hatDelta_ik for the
-// V commodities of vector q of vertex i, then h = Delta / delta_i.
-// RESID: write FP64 heights to h64 and also the per-block max |Delta|.
+// Work item (i, q) computes Delta_ik = sum_in f - sum_out f + hatDelta_ik for the
+// V commodities of vector q of vertex i, then h = Delta / delta_i. Items are
+// visited grid-stride in vertex order, so the two reads of an f row (by its
+// tail and by its head) fall close together in time.
+// Each block also sums max(0, Fsum_e - u_e)^2 over a grid-stride slice of
+// the arcs; zpart[b] and zpart[gridDim + b] receive the two partials.
+// RESID: write FP64 heights to h64 and the per-block max |Delta| (residual
+// report).
 template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
                                                 T *__restrict__ h, double *__restrict__ h64,
                                                 double *__restrict__ zpart,
                                                 double *__restrict__ maxpart,
-                                                const Ctrl *__restrict__ ctrl, int check_stop)
+                                                const double *__restrict__ Fsum,
+                                                const Ctrl *__restrict__ ctrl)
 {
-    if (check_stop && ctrl->stopped) return;
+    if (!RESID && ctrl->stopped) return;
     constexpr int V = VecT<T>::N;
     __shared__ double sh[8];
     const int nvec = g.Kp / V;
     const int64_t Kp = g.Kp;
-    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // Items are ordered commodity-chunk-major: chunk c holds vectors
+    // [c*CV, (c+1)*CV) of every vertex, vertices in order. All blocks in flight
+    // then work on one chunk of a window of consecutive vertices, so the two
+    // reads of an arc's chunk (by its tail and by its head) are close in time
+    // and the second is served by cache. Blocks are remapped so each XCD walks
+    // contiguous vertices (shared in-arc rows stay in that XCD's L2).
+    const int CV = g.height_cv;
+    const int64_t per_chunk = (int64_t)g.n * CV;
+    const int64_t total = per_chunk * ((nvec + CV - 1) / CV);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     double zs = 0.0, mx = 0.0;
-    if (gid < (int64_t)g.n * nvec) {
-        const int i = (int)(gid / nvec);
-        const int k0 = (int)(gid - (int64_t)i * nvec) * V;
+    for (int64_t gid = blk * 256 + threadIdx.x; gid < total; gid += (int64_t)gridDim.x * 256) {
+        const int64_t c = gid / per_chunk;
+        const int64_t rem = gid - c * per_chunk;
+        const int i = (int)(rem / CV);
+        const int q = (int)(c * CV + (rem - (int64_t)i * CV));
+        if (q >= nvec) continue;
+        const int k0 = q * V;
         double acc[V];
 #pragma unroll
         for (int w = 0; w < V; ++w) acc[w] = 0.0;
@@ -204,67 +275,28 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
             store_vec(h + (int64_t)i * Kp + k0, hv);
         }
     }
+    double ps = 0.0;
+    if constexpr (!RESID) {
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < g.m; e += gridDim.x * 256) {
+            const double over = Fsum[e] - g.u[e];
+            if (over > 0.0) ps += over * over;
+        }
+    }
     zs = wave_sum(zs);
     if (RESID) mx = wave_max(mx);
+    else ps = wave_sum(ps);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sh[w] = zs;
-        sh[4 + w] = mx;
+        sh[4 + w] = RESID ? mx : ps;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         zpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-        if (RESID) maxpart[blockIdx.x] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
-    }
-}
-
-// ----------------------------------------------------------------- objective + stop test
-// z = 1/2 sum_e max(0, Fsum_e - u_e)^2 + 1/2 sum_{i,k} Delta_ik h_ik (Algorithm 1).
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int64_t nz,
-                                                 const double *__restrict__ Fsum,
-                                                 const double *__restrict__ u, int m,
-                                                 Ctrl *__restrict__ ctrl, double *__restrict__ zlog)
-{
-    if (ctrl->stopped) return;
-    __shared__ double sh[2][16];
-    double a = 0.0, b = 0.0;
-    for (int64_t q = threadIdx.x; q < nz; q += 1024) a += zpart[q];
-    for (int q = threadIdx.x; q < m; q += 1024) {
-        const double over = Fsum[q] - u[q];
-        if (over > 0.0) b += over * over;
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[0][w] = a;
-        sh[1][w] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double A = 0.0, B = 0.0;
-        for (int q = 0; q < 16; ++q) {
-            A += sh[0][q];
-            B += sh[1][q];
-        }
-        const double zh = 0.5 * A, zp = 0.5 * B, z = zp + zh;
-        const int64_t ev = ctrl->evals;
-        zlog[ev & (kZLogCap - 1)] = z;
-        ctrl->evals = ev + 1;
-        ctrl->z = z;
-        ctrl->z_psi = zp;
-        ctrl->z_h = zh;
-        const bool fin = isfinite(z);
-        const bool stop = !fin || (ctrl->eps_obj > 0.0 && fabs(z - ctrl->z_prev) < ctrl->eps_obj) ||
-                          (ctrl->z_target > 0.0 && z <= ctrl->z_target);
-        if (!fin) ctrl->numeric = 1;
-        if (stop) {
-            ctrl->stopped = 1;
-        } else {
-            ctrl->z_prev = z;
-            ctrl->t_pass = ctrl->t;
-            ctrl->t = ctrl->t + 1;
-        }
+        if (RESID)
+            maxpart[blockIdx.x] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+        else
+            zpart[gridDim.x + blockIdx.x] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
     }
 }
 
@@ -413,8 +445,8 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     const double psi = F > u ? F - u : 0.0;
     const double b = beta[e];
 
-    T fv[NV][V], gv[NV][V];
-    double red[3] = {0.0, 0.0, 0.0};  // sum df, sum (df^2 - df g), sum of stepped values
+    T cand[NV][V];  // the stepped row f + df, written only if the step is accepted
+    double red[3] = {0.0, 0.0, 0.0};  // sum df, sum df (df - g), sum of stepped values
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int q = v * L + lane;
@@ -425,22 +457,18 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
             load_vec(hj + q * V, bb);
 #pragma unroll
             for (int w = 0; w < V; ++w) {
-                const T gg = a[w] - bb[w];
-                fv[v][w] = x[w];
-                gv[v][w] = gg;
+                const double gg = (double)(a[w] - bb[w]);
                 const double fx = (double)x[w];
-                const double step = b * ((double)gg - psi);
+                const double step = b * (gg - psi);
                 const double df = step > -fx ? step : -fx;
+                cand[v][w] = (T)(fx + df);
                 red[0] += df;
-                red[1] += df * (df - (double)gg);
-                red[2] += (double)(T)(fx + df);
+                red[1] += df * (df - gg);
+                red[2] += (double)cand[v][w];
             }
         } else {
 #pragma unroll
-            for (int w = 0; w < V; ++w) {
-                fv[v][w] = (T)0;
-                gv[v][w] = (T)0;
-            }
+            for (int w = 0; w < V; ++w) cand[v][w] = (T)0;
         }
     }
     group_sum<L, 3>(red, lds, phase);
@@ -459,17 +487,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int q = v * L + lane;
-            if (q < nvec) {
-                T o[V];
-#pragma unroll
-                for (int w = 0; w < V; ++w) {
-                    const double fx = (double)fv[v][w];
-                    const double step = b * ((double)gv[v][w] - psi);
-                    const double df = step > -fx ? step : -fx;
-                    o[w] = (T)(fx + df);
-                }
-                store_vec(fo + q * V, o);
-            }
+            if (q < nvec) store_vec(fo + q * V, cand[v]);
         }
     }
     if (lane == 0) {
@@ -643,6 +661,24 @@ __global__ __launch_bounds__(256) void k_pad(const double *__restrict__ src, D *
     }
 }
 
+// Plain 16-byte copy, the reference for what HBM delivers to a streaming kernel.
+// Each thread moves four independent 16-byte vectors per step.
+__global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src,
+                                              double2 *__restrict__ dst, int64_t count)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; q + 3 * stride < count; q += 4 * stride) {
+        const double2 a = src[q], b = src[q + stride], c = src[q + 2 * stride],
+                      d = src[q + 3 * stride];
+        dst[q] = a;
+        dst[q + stride] = b;
+        dst[q + 2 * stride] = c;
+        dst[q + 3 * stride] = d;
+    }
+    for (; q < count; q += stride) dst[q] = src[q];
+}
+
 // ----------------------------------------------------------------- launchers
 static inline unsigned grid_for(int64_t work, int64_t cap = 1 << 20)
 {
@@ -656,7 +692,8 @@ int64_t height_blocks(const DevGraph &g, int elem_bytes)
 {
     const int V = 16 / elem_bytes;
     const int64_t work = (int64_t)g.n * (g.Kp / V);
-    return work > 0 ? (work + 255) / 256 : 1;
+    int64_t b = work > 0 ? (work + 255) / 256 : 1;
+    return b < kHeightBlocksMax ? b : kHeightBlocksMax;
 }
 
 hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st)
@@ -666,15 +703,18 @@ hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t
 }
 
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
-                         const Ctrl *ctrl, bool check_stop, hipStream_t st)
+                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     if (fp64)
         k_height<double, false><<<nb, 256, 0, st>>>(g, (const double *)f, (double *)h, nullptr,
-                                                    zpart, nullptr, ctrl, check_stop ? 1 : 0);
+                                                    zpart, nullptr, Fsum, ctrl);
     else
         k_height<float, false><<<nb, 256, 0, st>>>(g, (const float *)f, (float *)h, nullptr, zpart,
-                                                   nullptr, ctrl, check_stop ? 1 : 0);
+                                                   nullptr, Fsum, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_reduce<<<1, 1024, 0, st>>>(zpart, (int)nb, ctrl, zlog);
     return hipGetLastError();
 }
 
@@ -684,17 +724,10 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     if (fp64)
         k_height<double, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
-                                                   maxpart, nullptr, 0);
+                                                   maxpart, nullptr, nullptr);
     else
         k_height<float, true><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart, maxpart,
-                                                  nullptr, 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const DevGraph &g, const double *zpart, int64_t nzpart,
-                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
-{
-    k_reduce<<<1, 1024, 0, st>>>(zpart, nzpart, Fsum, g.u, g.m, ctrl, zlog);
+                                                  nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -706,10 +739,12 @@ hipError_t launch_reduce(const DevGraph &g, const double *zpart, int64_t nzpart,
     X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
     X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
     X(64, 1) X(64, 2) X(64, 4) X(64, 8) \
-    X(128, 1) X(128, 2) X(128, 4) X(128, 8) \
-    X(256, 1) X(256, 2) X(256, 4) X(256, 8) \
-    X(512, 1) X(512, 2) X(512, 4) X(512, 8) \
-    X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 8)
+    X(128, 1) X(128, 2) X(128, 4) X(128, 8) X(128, 10) X(128, 12) X(128, 16) X(128, 20) \
+    X(256, 1) X(256, 2) X(256, 3) X(256, 4) X(256, 5) X(256, 6) X(256, 8) X(256, 10) \
+    X(256, 12) X(256, 16) X(256, 20) \
+    X(512, 1) X(512, 2) X(512, 3) X(512, 4) X(512, 5) X(512, 6) X(512, 8) X(512, 10) \
+    X(512, 12) \
+    X(1024, 1) X(1024, 2) X(1024, 3) X(1024, 4) X(1024, 5) X(1024, 6) X(1024, 8)
 
 bool tiling_supported(int lanes, int nv)
 {
@@ -801,6 +836,12 @@ hipError_t launch_resid(const DevGraph &g, bool fp64, const void *f, const doubl
         if (err != hipSuccess) return err;
     }
     k_resid_final<<<1, 1024, 0, st>>>(g, h64, zpart, nzpart, maxpart, arcpart, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t count16, hipStream_t st)
+{
+    k_copy<<<grid_for(count16, 4096), 256, 0, st>>>((const double2 *)src, (double2 *)dst, count16);
     return hipGetLastError();
 }
 
