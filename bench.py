@@ -72,6 +72,38 @@ def time_variant(pdr, inst, method, precision, steps, warmup):
                                               Kp=tiling[2]))
 
 
+def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=200):
+    """Run from f = 0 for about budget_s seconds (FP32-bulk runs hand over to the
+    FP64 polish by pdr_solve's rule); return the wall time and sweep count at
+    which z first fell to each rung, and the final state."""
+    out = {str(r): None for r in rungs}
+    with pdr.Context.from_instance(inst, method=method, precision=precision) as ctx:
+        pdr.device_synchronize()
+        t0 = time.perf_counter()
+        n32 = n64 = 0
+        evals = 0
+        while True:
+            a, b = ctx.solve(min(rungs), chunk, chunk)
+            n32 += a
+            n64 += b
+            now = time.perf_counter() - t0
+            res = ctx.residual()
+            new = res["evaluations"]
+            zl = ctx.z_log(evals, new - evals)
+            for r in rungs:
+                if out[str(r)] is None:
+                    hit = [q for q, z in enumerate(zl) if z <= r]
+                    if hit:
+                        # the pass that reached the rung, timed pro rata inside the chunk
+                        out[str(r)] = dict(sweeps=evals + hit[0],
+                                           seconds=now * (evals + hit[0] + 1) / max(new, 1))
+            evals = new
+            if res["stopped"] or now > budget_s or a + b == 0:
+                break
+    return dict(rungs=out, seconds=now, sweeps_fp32=n32, sweeps_fp64=n64, z_final=res["z"],
+                precision_final="fp64" if n64 or precision == pdr.FP64 else "fp32")
+
+
 def cpu_baseline(inst, sweeps):
     import oracle
     t0 = time.perf_counter()
@@ -94,6 +126,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=2 << 30,
                     help="buffer size of the plain-copy HBM reference (0: skip)")
+    ap.add_argument("--ttr-budget", type=float, default=6.0,
+                    help="seconds per variant of the time-to-residual ladder (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -156,6 +190,15 @@ def main():
             var[name] = dict(updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"],
                              kernel_ms_avg=r["kernel_ms_avg"], tiling=r["tiling"])
         out["variants"] = var
+    if args.ttr_budget > 0:
+        ttr = {}
+        for name, prec in (("fp64", pdr.FP64), ("fp32_polish", pdr.FP32_BULK)):
+            r = time_to_residual(pdr, inst, pdr.ESO, prec, args.ttr_budget,
+                                 [1e5, 1e4, 1e3, 1e2, 1e-8])
+            print(f"[bench] ttr eso {name}: {r}", file=sys.stderr, flush=True)
+            ttr[name] = r
+        out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
+                                       target=1e-8, **ttr)
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_sweeps} oracle sweeps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)

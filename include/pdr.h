@@ -88,6 +88,8 @@ typedef struct {
     double max_congestion; /* max psi_e */
     double farkas_gap;     /* sum_k d_k (h_sk - h_tk) - sum_e u_e max(0, max_k (h_ik - h_jk)) */
     double farkas_tol;     /* rounding margin of farkas_gap */
+    double z_fp32_floor;   /* FP32 storage: the objective that rounding each stored flow
+                              alone would leave (last pass); 0 in FP64 */
     int64_t sweeps_done;   /* arc updates applied since init (iteration counter t) */
     int64_t evaluations;   /* objective evaluations recorded in the z log */
     int32_t verdict;       /* pdr_verdict: INFEASIBLE if farkas_gap > farkas_tol,
@@ -132,17 +134,22 @@ pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_
 /*
  * Run passes until the objective z (evaluated in FP64 from the stored flows)
  * is <= z_target, or until max_sweeps passes in total (synchronizes).
- * In PDR_FP32_BULK the passes run in FP32 until the objective stalls -- the
- * smallest z of the last `window` evaluations is not below (1 - 1e-3) times
- * the smallest z before them -- then the flows are widened to FP64 exactly
- * (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
  * In PDR_FP64 it is pdr_sweep with the z_target stop test.
+ * In PDR_FP32_BULK the passes run in FP32 and, every `window` passes, the
+ * library estimates where FP32 rounding will stop the descent: every pass
+ * adds rounding noise of size z_noise (the objective that rounding each stored
+ * flow alone leaves, computed by the height kernel), and a descent that
+ * shrinks z by (1 - rate) per pass settles near z_noise / rate (rate measured
+ * over the last window). When z <= floor_factor * z_noise / rate (floor_factor
+ * <= 0 means 5), or when z stalls (the smallest z of the window is not below
+ * (1 - 1e-3) times the smallest before it), the flows are widened to FP64
+ * exactly (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
  * sweeps_fp32 / sweeps_fp64 (may be NULL) receive the passes run in each
  * precision. Errors: PDR_ERR_INVALID for z_target <= 0, max_sweeps < 0 or
  * window < 1; PDR_ERR_NUMERIC for a non-finite objective; PDR_ERR_DEVICE.
  */
 pdr_status pdr_solve(pdr_ctx *ctx, double z_target, int64_t max_sweeps, int64_t window,
-                     int64_t *sweeps_fp32, int64_t *sweeps_fp64);
+                     double floor_factor, int64_t *sweeps_fp32, int64_t *sweeps_fp64);
 
 /* Compute the FP64 residual report of the current flows (synchronizes).
  * Returns PDR_ERR_NUMERIC (and fills *out) if z is not finite. */

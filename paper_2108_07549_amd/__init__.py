@@ -60,7 +60,8 @@ class Residual(C.Structure):
     _fields_ = [("z", C.c_double), ("z_psi", C.c_double), ("z_h", C.c_double),
                 ("kkt_sq", C.c_double), ("max_abs_excess", C.c_double),
                 ("max_congestion", C.c_double), ("farkas_gap", C.c_double),
-                ("farkas_tol", C.c_double), ("sweeps_done", C.c_int64),
+                ("farkas_tol", C.c_double), ("z_fp32_floor", C.c_double),
+                ("sweeps_done", C.c_int64),
                 ("evaluations", C.c_int64), ("verdict", C.c_int32), ("stopped", C.c_int32)]
 
     def as_dict(self) -> dict:
@@ -84,7 +85,7 @@ def lib():
         L.pdr_default_options.restype = None
         L.pdr_init.argtypes = [C.POINTER(P), i32, i32, P, P, P, i32, P, P, P, C.POINTER(Options)]
         L.pdr_sweep.argtypes = [P, i64, dbl, dbl]
-        L.pdr_solve.argtypes = [P, dbl, i64, i64, C.POINTER(i64), C.POINTER(i64)]
+        L.pdr_solve.argtypes = [P, dbl, i64, i64, dbl, C.POINTER(i64), C.POINTER(i64)]
         L.pdr_residual.argtypes = [P, C.POINTER(Residual)]
         L.pdr_flows.argtypes = [P, P]
         L.pdr_flows_device.argtypes = [P, P, i32]
@@ -193,12 +194,13 @@ class Context:
     def sweep(self, max_sweeps: int, eps_obj: float = 0.0, z_target: float = 0.0):
         self._check(lib().pdr_sweep(self._h, int(max_sweeps), float(eps_obj), float(z_target)))
 
-    def solve(self, z_target: float, max_sweeps: int, window: int = 256):
-        """Run to z <= z_target; FP32-bulk contexts switch to the FP64 polish when
-        the objective stalls. Returns (passes in FP32, passes in FP64)."""
+    def solve(self, z_target: float, max_sweeps: int, window: int = 256,
+              floor_factor: float = 0.0):
+        """Run to z <= z_target; FP32-bulk contexts switch to the FP64 polish near
+        their rounding floor. Returns (passes in FP32, passes in FP64)."""
         a, b = C.c_int64(), C.c_int64()
         self._check(lib().pdr_solve(self._h, float(z_target), int(max_sweeps), int(window),
-                                    C.byref(a), C.byref(b)))
+                                    float(floor_factor), C.byref(a), C.byref(b)))
         return a.value, b.value
 
     def residual(self) -> dict:

@@ -24,6 +24,9 @@ constexpr int kMaxNv = 20;
 // Vectors per commodity chunk in the height kernel: small enough that the
 // rows read by a window of neighbouring vertices stay in L2.
 constexpr int kHeightChunkAuto = 64;
+// FP32 bulk hands over to the FP64 polish once z is within this factor of the
+// estimated FP32 floor z_noise / rate (see pdr_solve).
+constexpr double kFloorFactor = 5.0;
 }  // namespace
 
 struct pdr_ctx {
@@ -532,7 +535,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     } while (0)
     PDR_AL(c->Fsum, m);
     PDR_AL(c->beta, m);
-    PDR_AL(c->zpart, 2 * c->nzpart);
+    PDR_AL(c->zpart, 3 * c->nzpart);
     PDR_AL(c->maxpart, c->nzpart);
     PDR_AL(c->arcpart, 3 * (size_t)m);
     PDR_AL(c->resout, 8);
@@ -601,12 +604,13 @@ pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_ta
 }
 
 pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t window,
-                     int64_t *sweeps_fp32, int64_t *sweeps_fp64)
+                     double floor_factor, int64_t *sweeps_fp32, int64_t *sweeps_fp64)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
-    if (!(z_target > 0.0) || max_sweeps < 0 || window < 1)
+    if (!(z_target > 0.0) || max_sweeps < 0 || window < 1 || std::isnan(floor_factor))
         return fail(c, PDR_ERR_INVALID, "need z_target > 0, max_sweeps >= 0, window >= 1");
+    const double kappa = floor_factor > 0.0 ? floor_factor : kFloorFactor;
     int64_t n32 = 0, n64 = 0, total = 0;
     double best_before = std::numeric_limits<double>::infinity();
     std::vector<double> zl;
@@ -624,12 +628,23 @@ pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t wi
         total += ran;
         if (c->h_ctrl->numeric) return fail(c, PDR_ERR_NUMERIC, "the objective is not finite");
         if (c->h_ctrl->stopped || ran == 0) break;
-        if (c->precision == PDR_FP32_BULK && nev > 0) {
+        if (c->precision == PDR_FP32_BULK && nev > 1) {
             zl.resize((size_t)nev);
             st = pdr_z_log(c, ev0, nev, zl.data());
             if (st != PDR_OK) return st;
             const double cur = *std::min_element(zl.begin(), zl.end());
-            if (!(cur < (1.0 - 1e-3) * best_before)) {
+            // FP32 rounding adds noise of size z_noise every pass; a descent that
+            // shrinks z by the factor (1 - rate) per pass settles where the two
+            // balance, near z_noise / rate. Hand over well before that level,
+            // or when the objective stalls.
+            const double z_first = zl.front(), z_last = zl.back();
+            const double rate = (z_first > 0.0 && z_last > 0.0 && z_last < z_first)
+                                    ? std::log(z_first / z_last) / (double)(nev - 1)
+                                    : 0.0;
+            const double floor_est =
+                rate > 0.0 ? c->h_ctrl->z_noise / rate : std::numeric_limits<double>::infinity();
+            const bool near_floor = z_last <= kappa * floor_est;
+            if (near_floor || !(cur < (1.0 - 1e-3) * best_before)) {
                 st = pdr_set_precision(c, PDR_FP64);
                 if (st != PDR_OK) return st;
             }
@@ -711,6 +726,7 @@ pdr_status pdr_residual(pdr_ctx *c, pdr_residual_t *out)
     out->max_congestion = r[5];
     out->farkas_gap = r[6];
     out->farkas_tol = r[7];
+    out->z_fp32_floor = c->precision == PDR_FP32_BULK ? c->h_ctrl->z_noise : 0.0;
     out->sweeps_done = c->h_ctrl->t;
     out->evaluations = c->h_ctrl->evals;
     out->stopped = c->h_ctrl->stopped;

@@ -19,6 +19,7 @@ struct Ctrl {
     double eps_obj;      // stop if |z - z_prev| < eps_obj (when > 0)
     double z_target;     // stop if z <= z_target (when > 0)
     double z, z_psi, z_h;  // last evaluated objective and its two parts
+    double z_noise;        // FP32 storage: objective left by rounding the flows alone
 };
 
 constexpr int64_t kZLogCap = int64_t(1) << 20;

@@ -87,6 +87,8 @@ __device__ __forceinline__ double wave_max(double v)
 
 // Largest number of values reduced at once by one group_sum call.
 constexpr int kRedMax = 4;
+// Unit roundoff of FP32.
+constexpr double kFp32Unit = 5.9604644775390625e-08;
 
 // Sum of N values over the L lanes of a group; every lane receives the same
 // bits (butterfly partners add the same two operands; the cross-wave step
@@ -141,34 +143,42 @@ __global__ void k_begin(Ctrl *ctrl, double eps_obj, double z_target)
 // One block: z = 1/2 sum of the height kernel's per-block partials of
 // Delta * h and of max(0, Fsum_e - u_e)^2 (Algorithm 1), the z log, the stop
 // test of Algorithm 1 (|z - z_prev| < eps_obj) or z <= z_target, and the
-// iteration counter. The partials come two per height block, so this block
-// reads at most 2 * kHeightBlocksMax values.
+// iteration counter. The partials come three per height block, so this block
+// reads at most 3 * kHeightBlocksMax values. The third is, for FP32 storage,
+// z_noise = 1/2 sum_{i,k} (u32 a_ik)^2 / delta_i with a_ik the sum of the
+// magnitudes entering Delta_ik and u32 = 2^-24: the objective that rounding
+// each stored flow alone would leave; the FP32 run cannot get far below it.
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int nz,
                                                  Ctrl *__restrict__ ctrl,
                                                  double *__restrict__ zlog)
 {
     if (ctrl->stopped) return;
-    __shared__ double sh[2][16];
-    double a = 0.0, b = 0.0;
+    __shared__ double sh[3][16];
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int q = threadIdx.x; q < nz; q += 1024) {
         a += zpart[q];
         b += zpart[nz + q];
+        c += zpart[2 * nz + q];
     }
     a = wave_sum(a);
     b = wave_sum(b);
+    c = wave_sum(c);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sh[0][w] = a;
         sh[1][w] = b;
+        sh[2][w] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double A = 0.0, B = 0.0;
+        double A = 0.0, B = 0.0, Cn = 0.0;
         for (int q = 0; q < 16; ++q) {
             A += sh[0][q];
             B += sh[1][q];
+            Cn += sh[2][q];
         }
         const double zh = 0.5 * A, zp = 0.5 * B, z = zp + zh;
+        ctrl->z_noise = 0.5 * Cn;
         const int64_t ev = ctrl->evals;
         zlog[ev & (kZLogCap - 1)] = z;
         ctrl->evals = ev + 1;
@@ -208,7 +218,11 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
 {
     if (!RESID && ctrl->stopped) return;
     constexpr int V = VecT<T>::N;
-    __shared__ double sh[8];
+    // FP32 storage: also accumulate the size of the rounding noise the stored
+    // flows carry into each excess (see k_reduce)
+    constexpr bool kNoise = !RESID && sizeof(T) == 4;
+    __shared__ double sh[12];
+    double ns = 0.0;
     const int nvec = g.Kp / V;
     const int64_t Kp = g.Kp;
     // Items are ordered commodity-chunk-major: chunk c holds vectors
@@ -229,23 +243,29 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
         const int q = (int)(c * CV + (rem - (int64_t)i * CV));
         if (q >= nvec) continue;
         const int k0 = q * V;
-        double acc[V];
+        double acc[V], mag[V];
 #pragma unroll
-        for (int w = 0; w < V; ++w) acc[w] = 0.0;
+        for (int w = 0; w < V; ++w) acc[w] = mag[w] = 0.0;
         const int p0 = g.in_ptr[i], p1 = g.in_ptr[i + 1];
         for (int p = p0; p < p1; ++p) {
             const int64_t e = g.in_idx[p];
             T x[V];
             load_vec(f + e * Kp + k0, x);
 #pragma unroll
-            for (int w = 0; w < V; ++w) acc[w] += (double)x[w];
+            for (int w = 0; w < V; ++w) {
+                acc[w] += (double)x[w];
+                if constexpr (kNoise) mag[w] += fabs((double)x[w]);
+            }
         }
         const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
         for (int e = e0; e < e1; ++e) {
             T x[V];
             load_vec(f + (int64_t)e * Kp + k0, x);
 #pragma unroll
-            for (int w = 0; w < V; ++w) acc[w] -= (double)x[w];
+            for (int w = 0; w < V; ++w) {
+                acc[w] -= (double)x[w];
+                if constexpr (kNoise) mag[w] += fabs((double)x[w]);
+            }
         }
         const int j0 = g.inj_ptr[i], j1 = g.inj_ptr[i + 1];
         for (int p = j0; p < j1; ++p) {
@@ -253,7 +273,10 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
             const double val = g.inj_val[p];
 #pragma unroll
             for (int w = 0; w < V; ++w)
-                if (w == k) acc[w] += val;
+                if (w == k) {
+                    acc[w] += val;
+                    if constexpr (kNoise) mag[w] += fabs(val);
+                }
         }
         const int dg = g.deg[i];
         T hv[V];
@@ -265,6 +288,10 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
             hv[w] = (T)hh;
             zs += acc[w] * hh;
             if (RESID) mx = fmax(mx, fabs(acc[w]));
+            if constexpr (kNoise) {
+                const double r = kFp32Unit * mag[w];
+                if (dg > 0) ns += r * r / (double)dg;
+            }
         }
         if constexpr (RESID) {
             double *dst = h64 + (int64_t)i * Kp + k0;
@@ -285,18 +312,22 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
     zs = wave_sum(zs);
     if (RESID) mx = wave_max(mx);
     else ps = wave_sum(ps);
+    if constexpr (kNoise) ns = wave_sum(ns);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sh[w] = zs;
         sh[4 + w] = RESID ? mx : ps;
+        sh[8 + w] = ns;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         zpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-        if (RESID)
+        if (RESID) {
             maxpart[blockIdx.x] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
-        else
+        } else {
             zpart[gridDim.x + blockIdx.x] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+            zpart[2 * gridDim.x + blockIdx.x] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
+        }
     }
 }
 
