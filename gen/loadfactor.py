@@ -67,7 +67,8 @@ def _shortest_paths(n, tails, heads, lengths, s, t, chunk=512):
 
 
 def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: bool = False,
-                       time_limit: float = 7200.0, kappa: float = 12.0):
+                       time_limit: float = 7200.0, kappa: float = 12.0, mu_lo0: float = 0.0,
+                       on_iter=None):
     """Return dict(mu_hi, mu_lo, iters, columns) for the instance's demands.
 
     Columns come from two pricing rules per iteration: shortest paths under the
@@ -107,7 +108,7 @@ def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: boo
             added += 1
         return added
 
-    mu_lo = 0.0
+    mu_lo = float(mu_lo0)  # any valid lower bound known in advance (e.g. a cut bound)
     mu_hi = np.inf
     it = 0
     for it in range(1, max_iter + 1):
@@ -142,6 +143,8 @@ def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: boo
         if verbose:
             print(f"[cg] it {it} cols {P} mu_hi {mu_hi:.6g} mu_lo {mu_lo:.6g} "
                   f"gap {mu_hi / mu_lo - 1:.2e} t {time.time() - t0:.1f}s", flush=True)
+        if on_iter is not None:
+            on_iter(dict(mu_hi=mu_hi, mu_lo=mu_lo, iters=it, columns=P))
         if mu_hi <= mu_lo * (1.0 + gap) or time.time() - t0 > time_limit:
             break
         # drop columns idle for three masters

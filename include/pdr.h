@@ -76,6 +76,12 @@ typedef struct {
                               < 0 = launch every kernel directly */
     int32_t height_chunk;  /* 16-byte vectors per commodity chunk in the height
                               kernel: 0 = automatic, else a power of two 1..256 */
+    int32_t cluster_size;  /* vertices per locality cluster of the visiting order:
+                              0 = automatic (64), 1 = the caller's vertex order */
+    int32_t height_blocks; /* blocks of the grid-stride height kernel: 0 = automatic,
+                              else 1..2048 (tuning) */
+    int32_t height_unroll; /* incident rows each height-kernel thread loads before
+                              summing: 0 = automatic, 1, 2 or 4 (tuning) */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */

@@ -24,6 +24,12 @@ constexpr int kMaxNv = 20;
 // Vectors per commodity chunk in the height kernel: small enough that the
 // rows read by a window of neighbouring vertices stay in L2.
 constexpr int kHeightChunkAuto = 64;
+// Blocks of the grid-stride height kernel.
+constexpr int kHeightGridAuto = 2048;
+// Incident rows each height-kernel thread loads before summing them.
+constexpr int kHeightUnrollAuto = 4;
+// Vertices per locality cluster of the visiting order.
+constexpr int kClusterAuto = 64;
 // FP32 bulk hands over to the FP64 polish once z is within this factor of the
 // estimated FP32 floor z_noise / rate (see pdr_solve).
 constexpr double kFloorFactor = 5.0;
@@ -43,6 +49,9 @@ struct pdr_ctx {
     Tiling tiling{1, 1};
     int32_t graph_sweeps = 32;             // passes per captured graph; 0 = no graphs
     int32_t req_height_chunk = 0;          // 0 = automatic
+    int32_t cluster_size = 64;             // vertices per locality cluster; 1 = natural order
+    int32_t req_height_grid = 0;           // 0 = automatic
+    int32_t req_height_unroll = 0;         // 0 = automatic
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
@@ -52,7 +61,7 @@ struct pdr_ctx {
     // instance arrays (device)
     int32_t *d_row_ptr = nullptr, *d_tails = nullptr, *d_heads = nullptr, *d_in_ptr = nullptr,
             *d_in_idx = nullptr, *d_deg = nullptr, *d_inj_ptr = nullptr, *d_inj_k = nullptr,
-            *d_s = nullptr, *d_t = nullptr;
+            *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr;
     double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
     // run state (device)
     double *f64 = nullptr, *h64 = nullptr;
@@ -193,6 +202,8 @@ void set_height_chunk(pdr_ctx *c)
     const int64_t nvec = c->Kp / vec_of(c->precision);
     const int cap = c->req_height_chunk > 0 ? c->req_height_chunk : kHeightChunkAuto;
     c->g.height_cv = std::min<int>(cap, pow2ceil(nvec));
+    c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : kHeightGridAuto;
+    c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : kHeightUnrollAuto;
 }
 
 void *cur_f(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->f64 : (void *)c->f32; }
@@ -239,6 +250,75 @@ pdr_status push_ctrl(pdr_ctx *c)
     PDR_CHECK(c, hipMemcpyAsync(c->ctrl, c->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
     PDR_CHECK(c, hipStreamSynchronize(c->stream));
     return PDR_OK;
+}
+
+// Processing order with locality: vertices are grouped into clusters of up to
+// T vertices grown by breadth-first search over the undirected adjacency, the
+// cluster seeds taken in a breadth-first order of the whole graph, so that
+// neighbouring clusters follow each other. The kernels visit vertices
+// (height) and out-arcs (arc update) in this order, so the rows of f and h
+// that several vertices or arcs share are read close together in time. Only
+// the visiting order changes; the data layout and every result are the same.
+void locality_order(int32_t n, const int32_t *rp, const int32_t *col,
+                    const std::vector<int32_t> &in_ptr, const std::vector<int32_t> &in_idx,
+                    const std::vector<int32_t> &tails, int32_t T, std::vector<int32_t> &vorder,
+                    std::vector<int32_t> &aorder)
+{
+    vorder.clear();
+    aorder.clear();
+    if (T <= 1) {
+        for (int32_t v = 0; v < n; ++v) vorder.push_back(v);
+    } else {
+        std::vector<char> seen(n, 0), taken(n, 0);
+        std::vector<int32_t> seeds, queue;
+        seeds.reserve(n);
+        // global breadth-first order (over every component)
+        for (int32_t r = 0; r < n; ++r) {
+            if (seen[r]) continue;
+            size_t head = seeds.size();
+            seeds.push_back(r);
+            seen[r] = 1;
+            while (head < seeds.size()) {
+                const int32_t v = seeds[head++];
+                auto visit = [&](int32_t w) {
+                    if (!seen[w]) {
+                        seen[w] = 1;
+                        seeds.push_back(w);
+                    }
+                };
+                for (int32_t e = rp[v]; e < rp[v + 1]; ++e) visit(col[e]);
+                for (int32_t p = in_ptr[v]; p < in_ptr[v + 1]; ++p) visit(tails[in_idx[p]]);
+            }
+        }
+        std::vector<int32_t> stamp(n, -1);
+        int32_t cl = 0;
+        for (int32_t sd : seeds) {
+            if (taken[sd]) continue;
+            queue.clear();
+            queue.push_back(sd);
+            stamp[sd] = cl;
+            size_t head = 0;
+            int32_t size = 0;
+            while (head < queue.size() && size < T) {
+                const int32_t v = queue[head++];
+                if (taken[v]) continue;
+                taken[v] = 1;
+                vorder.push_back(v);
+                ++size;
+                auto visit = [&](int32_t w) {
+                    if (!taken[w] && stamp[w] != cl) {
+                        stamp[w] = cl;
+                        queue.push_back(w);
+                    }
+                };
+                for (int32_t e = rp[v]; e < rp[v + 1]; ++e) visit(col[e]);
+                for (int32_t p = in_ptr[v]; p < in_ptr[v + 1]; ++p) visit(tails[in_idx[p]]);
+            }
+            ++cl;
+        }
+    }
+    for (int32_t v : vorder)
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) aorder.push_back(e);
 }
 
 pdr::AgdParams agd_params(const pdr_ctx *c)
@@ -329,6 +409,9 @@ void pdr_default_options(pdr_options *opt)
     opt->vec_per_lane = 0;
     opt->graph_sweeps = 0;
     opt->height_chunk = 0;
+    opt->cluster_size = 0;
+    opt->height_blocks = 0;
+    opt->height_unroll = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -406,6 +489,12 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     if (!(opt.z_feasible_tol >= 0) || !std::isfinite(opt.z_feasible_tol))
         return invalid("z_feasible_tol must be finite and >= 0");
     if (opt.lanes_per_arc < 0 || opt.vec_per_lane < 0) return invalid("negative tiling request");
+    if (opt.cluster_size < 0) return invalid("cluster_size must be >= 0");
+    if (opt.height_unroll != 0 && opt.height_unroll != 1 && opt.height_unroll != 2 &&
+        opt.height_unroll != 4)
+        return invalid("height_unroll must be 0, 1, 2 or 4");
+    if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
+        return invalid("height_blocks must be 0 or 1..2048");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
         (opt.height_chunk & (opt.height_chunk - 1)) != 0)
         return invalid("height_chunk must be 0 or a power of two up to 256");
@@ -424,6 +513,9 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->req_nv = opt.vec_per_lane;
     c->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
     c->req_height_chunk = opt.height_chunk;
+    c->cluster_size = opt.cluster_size == 0 ? kClusterAuto : opt.cluster_size;
+    c->req_height_grid = opt.height_blocks;
+    c->req_height_unroll = opt.height_unroll;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
         if (st != PDR_OK) return init_fail(c, st, out);
@@ -492,6 +584,20 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
         }
     }
 
+    std::vector<int32_t> vorder, aorder;
+    locality_order(n, rp32.data(), col, in_ptr, in_idx, tails, c->cluster_size, vorder, aorder);
+    {
+        // the kernels index through these arrays: they must be permutations
+        std::vector<char> hit_v(n, 0), hit_a(m > 0 ? m : 1, 0);
+        bool ok = (int64_t)vorder.size() == n && (int64_t)aorder.size() == m;
+        for (int32_t v : vorder) ok = ok && v >= 0 && v < n && !hit_v[v] && (hit_v[v] = 1);
+        for (int32_t e : aorder) ok = ok && e >= 0 && e < m && !hit_a[e] && (hit_a[e] = 1);
+        if (!ok) {
+            c->err = "internal error: the visiting order is not a permutation";
+            return init_fail(c, PDR_ERR_STATE, out);
+        }
+    }
+
     auto oom_or_dev = [&](hipError_t err, const char *what) {
         if (err == hipErrorOutOfMemory) {
             c->err = std::string("out of device memory: ") + what;
@@ -518,16 +624,18 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     PDR_UP(c->d_s, s, K);
     PDR_UP(c->d_t, t, K);
     PDR_UP(c->d_d, d, K);
+    PDR_UP(c->d_vorder, vorder.data(), n);
+    PDR_UP(c->d_aorder, aorder.data(), m);
 #undef PDR_UP
-    c->g = DevGraph{n,           m,         K,           c->Kp,        0,
+    c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,
                     c->d_row_ptr, c->d_tails, c->d_heads, c->d_in_ptr, c->d_in_idx,
                     c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
-                    c->d_s,       c->d_t,     c->d_d};
+                    c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder};
     set_height_chunk(c);
 
     pdr_status st = ensure_buffers(c, c->precision);
     if (st != PDR_OK) return init_fail(c, st, out);
-    c->nzpart = pdr::height_blocks(c->g, 8);  // FP64 needs the most blocks
+    c->nzpart = pdr::kHeightBlocksMax;  // partials of any height grid
 #define PDR_AL(ptr, cnt)                                     \
     do {                                                     \
         hipError_t _e = dalloc(c, &(ptr), (size_t)(cnt));    \

@@ -31,6 +31,8 @@ constexpr int64_t kHeightBlocksMax = 2048;
 struct DevGraph {
     int32_t n, m, K, Kp;
     int32_t height_cv;       // vectors per commodity chunk in the height kernel
+    int32_t height_grid;     // blocks of the height kernel (<= kHeightBlocksMax)
+    int32_t height_unroll;   // incident rows loaded together per thread (1, 2 or 4)
     const int32_t *row_ptr;  // n+1: out-arcs of i are [row_ptr[i], row_ptr[i+1])
     const int32_t *tails;    // m
     const int32_t *heads;    // m
@@ -43,6 +45,8 @@ struct DevGraph {
     const double *u;         // m capacities
     const int32_t *s, *t;    // K
     const double *d;         // K
+    const int32_t *vorder;   // n: order in which the height kernel visits vertices
+    const int32_t *aorder;   // m: order in which the arc kernels visit arcs
 };
 
 struct AgdParams {

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpar
 // the arcs; zpart[b] and zpart[gridDim + b] receive the two partials.
 // RESID: write FP64 heights to h64 and the per-block max |Delta| (residual
 // report).
-template <typename T, bool RESID>
+template <typename T, bool RESID, int U>
 __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
                                                 T *__restrict__ h, double *__restrict__ h64,
                                                 double *__restrict__ zpart,
@@ -239,33 +239,49 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
     for (int64_t gid = blk * 256 + threadIdx.x; gid < total; gid += (int64_t)gridDim.x * 256) {
         const int64_t c = gid / per_chunk;
         const int64_t rem = gid - c * per_chunk;
-        const int i = (int)(rem / CV);
-        const int q = (int)(c * CV + (rem - (int64_t)i * CV));
+        const int pos = (int)(rem / CV);
+        const int i = g.vorder[pos];
+        const int q = (int)(c * CV + (rem - (int64_t)pos * CV));
         if (q >= nvec) continue;
         const int k0 = q * V;
         double acc[V], mag[V];
 #pragma unroll
         for (int w = 0; w < V; ++w) acc[w] = mag[w] = 0.0;
+        // in-arcs (+) then out-arcs (-), U rows loaded before they are summed
+        // (the summation order is the same for every U)
         const int p0 = g.in_ptr[i], p1 = g.in_ptr[i + 1];
-        for (int p = p0; p < p1; ++p) {
-            const int64_t e = g.in_idx[p];
-            T x[V];
-            load_vec(f + e * Kp + k0, x);
+        for (int p = p0; p < p1; p += U) {
+            T x[U][V];
 #pragma unroll
-            for (int w = 0; w < V; ++w) {
-                acc[w] += (double)x[w];
-                if constexpr (kNoise) mag[w] += fabs((double)x[w]);
+            for (int b = 0; b < U; ++b) {
+                const int64_t e = g.in_idx[p + b < p1 ? p + b : p];
+                load_vec(f + e * Kp + k0, x[b]);
             }
+#pragma unroll
+            for (int b = 0; b < U; ++b)
+                if (p + b < p1) {
+#pragma unroll
+                    for (int w = 0; w < V; ++w) {
+                        acc[w] += (double)x[b][w];
+                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
+                    }
+                }
         }
         const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
-        for (int e = e0; e < e1; ++e) {
-            T x[V];
-            load_vec(f + (int64_t)e * Kp + k0, x);
+        for (int e = e0; e < e1; e += U) {
+            T x[U][V];
 #pragma unroll
-            for (int w = 0; w < V; ++w) {
-                acc[w] -= (double)x[w];
-                if constexpr (kNoise) mag[w] += fabs((double)x[w]);
-            }
+            for (int b = 0; b < U; ++b)
+                load_vec(f + (int64_t)(e + b < e1 ? e + b : e) * Kp + k0, x[b]);
+#pragma unroll
+            for (int b = 0; b < U; ++b)
+                if (e + b < e1) {
+#pragma unroll
+                    for (int w = 0; w < V; ++w) {
+                        acc[w] -= (double)x[b][w];
+                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
+                    }
+                }
         }
         const int j0 = g.inj_ptr[i], j1 = g.inj_ptr[i + 1];
         for (int p = j0; p < j1; ++p) {
@@ -362,8 +378,9 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
-    const int64_t e = blk * S::GPB + grp;
-    if (L <= 64 && e >= g.m) return;
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
     const T *fe = f + e * Kp;
@@ -464,8 +481,9 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
-    const int64_t e = blk * S::GPB + grp;
-    if (L <= 64 && e >= g.m) return;
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
     const T *fe = f + e * Kp;
@@ -544,8 +562,9 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
-    const int64_t e = blk * S::GPB + grp;
-    if (L <= 64 && e >= g.m) return;
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    const int64_t e = g.aorder[slot];
     const int nvec = g.Kp / V;
     const T *fe = f + e * (int64_t)g.Kp;
     double fs[1] = {0.0};
@@ -724,7 +743,8 @@ int64_t height_blocks(const DevGraph &g, int elem_bytes)
     const int V = 16 / elem_bytes;
     const int64_t work = (int64_t)g.n * (g.Kp / V);
     int64_t b = work > 0 ? (work + 255) / 256 : 1;
-    return b < kHeightBlocksMax ? b : kHeightBlocksMax;
+    const int64_t cap = g.height_grid > 0 ? g.height_grid : kHeightBlocksMax;
+    return b < cap ? b : cap;
 }
 
 hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st)
@@ -733,16 +753,26 @@ hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t
     return hipGetLastError();
 }
 
+#define PDR_HEIGHT_UNROLL(X) X(1) X(2) X(4)
+
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
                          const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
-    if (fp64)
-        k_height<double, false><<<nb, 256, 0, st>>>(g, (const double *)f, (double *)h, nullptr,
-                                                    zpart, nullptr, Fsum, ctrl);
-    else
-        k_height<float, false><<<nb, 256, 0, st>>>(g, (const float *)f, (float *)h, nullptr, zpart,
-                                                   nullptr, Fsum, ctrl);
+    bool launched = false;
+#define PDR_H(U_)                                                                               \
+    if (!launched && g.height_unroll == U_) {                                                   \
+        if (fp64)                                                                               \
+            k_height<double, false, U_><<<nb, 256, 0, st>>>(g, (const double *)f, (double *)h,  \
+                                                            nullptr, zpart, nullptr, Fsum, ctrl); \
+        else                                                                                    \
+            k_height<float, false, U_><<<nb, 256, 0, st>>>(g, (const float *)f, (float *)h,     \
+                                                           nullptr, zpart, nullptr, Fsum, ctrl); \
+        launched = true;                                                                        \
+    }
+    PDR_HEIGHT_UNROLL(PDR_H)
+#undef PDR_H
+    if (!launched) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_reduce<<<1, 1024, 0, st>>>(zpart, (int)nb, ctrl, zlog);
@@ -754,11 +784,11 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     if (fp64)
-        k_height<double, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
-                                                   maxpart, nullptr, nullptr);
+        k_height<double, true, 4><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
+                                                      maxpart, nullptr, nullptr);
     else
-        k_height<float, true><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart, maxpart,
-                                                  nullptr, nullptr);
+        k_height<float, true, 4><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart,
+                                                     maxpart, nullptr, nullptr);
     return hipGetLastError();
 }
 
