@@ -44,7 +44,7 @@ typedef enum {
     PDR_ERR_NUMERIC = 5  /* the objective became non-finite */
 } pdr_status;
 
-typedef enum { PDR_ESO = 0, PDR_AGD = 1 } pdr_method;
+typedef enum { PDR_ESO = 0, PDR_AGD = 1, PDR_GDM = 2 } pdr_method;
 
 /* PDR_FP64: f and h stored and updated in FP64.
  * PDR_FP32_BULK: f and h stored and updated in FP32; excess accumulation,
@@ -53,19 +53,23 @@ typedef enum { PDR_FP64 = 0, PDR_FP32_BULK = 1 } pdr_precision;
 
 typedef enum { PDR_UNDECIDED = 0, PDR_FEASIBLE = 1, PDR_INFEASIBLE = 2 } pdr_verdict;
 
-/* Parameters of Algorithm 3. Defaults are the paper's experimental settings
- * (Section 7.2): beta_init 0.25, beta_min 1/K, beta_max 0.5, alpha_inc 2,
- * alpha_dec 0.5; the increase period is 10 iterations (Algorithm 3).
- * beta_min <= 0 means 1/K. */
+/* Parameters of Algorithms 3 (AGD) and 4 (GDM). Defaults are the paper's
+ * experimental settings (Section 7.2): AGD beta_init 0.25, beta_min 1/K,
+ * beta_max 0.5, alpha_inc 2, alpha_dec 0.5; GDM beta_init 0.1, beta_min 1/K,
+ * beta_max 0.2, alpha_inc 2, alpha_dec 0.5, momentum gamma 0.9; the increase
+ * period is 10 iterations (Algorithms 3, 4). beta_min <= 0 means 1/K. gamma is
+ * used by GDM only and must lie in [0, 1). */
 typedef struct {
     double beta_init, beta_min, beta_max, alpha_inc, alpha_dec;
     int32_t inc_period;
+    double gamma;
 } pdr_agd_params;
 
 typedef struct {
     int32_t method;        /* pdr_method */
     int32_t precision;     /* pdr_precision */
-    pdr_agd_params agd;
+    pdr_agd_params agd;    /* used by PDR_AGD */
+    pdr_agd_params gdm;    /* used by PDR_GDM */
     double z_feasible_tol; /* verdict FEASIBLE needs z <= this (default 1e-8) */
     void *stream;          /* hipStream_t to run on, or NULL */
     int32_t lanes_per_arc; /* 0: automatic; else a power of two 1..1024 (tuning) */
@@ -81,7 +85,7 @@ typedef struct {
     int32_t height_blocks; /* blocks of the grid-stride height kernel: 0 = automatic,
                               else 1..2048 (tuning) */
     int32_t height_unroll; /* incident rows each height-kernel thread loads before
-                              summing: 0 = automatic, 1, 2 or 4 (tuning) */
+                              summing: 0 = automatic, 1, 2, 4 or 8 (tuning) */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */
@@ -103,7 +107,7 @@ typedef struct {
     int32_t stopped;       /* 1 if the last pdr_sweep call ended on its stop test */
 } pdr_residual_t;
 
-/* Fill *opt with the defaults (ESO, FP64, the paper's AGD parameters,
+/* Fill *opt with the defaults (ESO, FP64, the paper's AGD and GDM parameters,
  * z_feasible_tol 1e-8, stream NULL, automatic tiling). */
 void pdr_default_options(pdr_options *opt);
 
@@ -126,7 +130,8 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
                     const int32_t *t, const double *d, const pdr_options *opt);
 
 /*
- * Enqueue up to max_sweeps passes of Algorithm 1 (ESO) or Algorithm 3 (AGD).
+ * Enqueue up to max_sweeps passes of Algorithm 1 (ESO), Algorithm 3 (AGD) or
+ * Algorithm 4 (GDM).
  * Each pass computes h, psi and z from the current flows, records z in the z
  * log, stops if eps_obj > 0 and |z - z_prev| < eps_obj (z_prev = +inf before
  * the first pass since init) or if z_target > 0 and z <= z_target, and
@@ -172,8 +177,12 @@ pdr_status pdr_flows_device(pdr_ctx *ctx, void *dev_out, int32_t fp64);
  * host (synchronizes). */
 pdr_status pdr_heights(pdr_ctx *ctx, double *host_out);
 
-/* Copy the AGD learning rates beta[m] to the host (synchronizes). */
+/* Copy the AGD/GDM learning rates beta[m] to the host (synchronizes). */
 pdr_status pdr_learning_rates(pdr_ctx *ctx, double *host_out);
+
+/* Copy the GDM velocities v[m*K] (Algorithm 4) as FP64 to the host
+ * (synchronizes). PDR_ERR_STATE for a context that is not PDR_GDM. */
+pdr_status pdr_velocities(pdr_ctx *ctx, double *host_out);
 
 /* Copy z log entries [first, first + count) to host_out (synchronizes).
  * Entry q is the objective of the q-th evaluation since init. The log keeps
@@ -185,11 +194,12 @@ pdr_status pdr_z_log(pdr_ctx *ctx, int64_t first, int64_t count, double *host_ou
  * iteration counter, z_prev and learning rates are kept. */
 pdr_status pdr_set_precision(pdr_ctx *ctx, int32_t precision);
 
-/* Replace the run state: flows f[m*K] (FP64, >= 0, finite), AGD rates
- * beta[m] (may be NULL to keep), iteration counter t and z_prev
- * (+inf to restart the stop test). Used to resume a saved run. */
-pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, int64_t t,
-                         double z_prev);
+/* Replace the run state: flows f[m*K] (FP64, >= 0, finite), AGD/GDM rates
+ * beta[m] (may be NULL to keep), GDM velocities v[m*K] (finite; may be NULL to
+ * keep; ignored by other methods), iteration counter t and z_prev (+inf to
+ * restart the stop test). Used to resume a saved run. */
+pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, const double *v,
+                         int64_t t, double z_prev);
 
 /* Measurement: run `sweeps` passes like pdr_sweep without a stop test,
  * recording HIP events around every kernel on the context stream. On return

@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "pdr_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-ESO, AGD = 0, 1
+ESO, AGD, GDM = 0, 1, 2
 VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
 
 
@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 
 class _AgdParams(C.Structure):
     _fields_ = [("beta_init", C.c_double), ("beta_min", C.c_double), ("beta_max", C.c_double),
-                ("alpha_inc", C.c_double), ("alpha_dec", C.c_double), ("inc_period", C.c_int32)]
+                ("alpha_inc", C.c_double), ("alpha_dec", C.c_double), ("inc_period", C.c_int32),
+                ("gamma", C.c_double)]
 
 
 def lib():
@@ -60,8 +61,11 @@ def lib():
         L.orc_agd_edge.argtypes = [i32, P, P, P, dbl, dbl, dbl, i64, P, dbl, dbl, dbl, dbl, i32,
                                    P, P]
         L.orc_agd_edge.restype = C.c_int
+        L.orc_gdm_edge.argtypes = [i32, P, P, P, P, dbl, dbl, dbl, i64, P, dbl, dbl, dbl, dbl,
+                                   i32, dbl, P, P, P]
+        L.orc_gdm_edge.restype = C.c_int
         L.orc_run.argtypes = [i32, i32, P, P, P, i32, P, P, P, i32, C.POINTER(_AgdParams), i64,
-                              dbl, dbl, P, P, P, P, P, P]
+                              dbl, dbl, P, P, P, P, P, P, P]
         L.orc_run.restype = i64
         L.orc_report.argtypes = [i32, i32, P, P, P, i32, P, P, P, P, dbl, P]
         L.orc_report.restype = i32
@@ -140,6 +144,25 @@ def eso_edge(hi, hj, fe, u):
     return out, float(psi[0]), float(r[0]), bool(cg)
 
 
+def gdm_edge(hi, hj, fe, ve, u, t, beta, params=None):
+    """One GDM arc step: returns (f_new, v_new, beta_new, accepted, dz)."""
+    hi, hj, fe, ve = (_c(x, np.float64) for x in (hi, hj, fe, ve))
+    K = hi.shape[0]
+    p = default_gdm_params(K) if params is None else params
+    F = 0.0
+    for x in fe.tolist():
+        F += x
+    psi = max(0.0, F - u)
+    b = np.array([beta], np.float64)
+    fo = np.zeros(K)
+    vo = np.zeros(K)
+    dz = np.zeros(1)
+    a = lib().orc_gdm_edge(K, _p(hi), _p(hj), _p(fe), _p(ve), F, float(u), psi, int(t), _p(b),
+                           p["beta_min"], p["beta_max"], p["alpha_inc"], p["alpha_dec"],
+                           int(p["inc_period"]), p["gamma"], _p(fo), _p(vo), _p(dz))
+    return fo, vo, float(b[0]), bool(a), float(dz[0])
+
+
 def agd_edge(hi, hj, fe, u, t, beta, params=None):
     """One AGD arc step: returns (f_new, beta_new, accepted, dz)."""
     hi, hj, fe = (_c(x, np.float64) for x in (hi, hj, fe))
@@ -163,17 +186,30 @@ def agd_edge(hi, hj, fe, u, t, beta, params=None):
 def default_agd_params(K: int) -> dict:
     """AGD parameters of the paper's experiments (Section 7.2)."""
     return dict(beta_init=0.25, beta_min=1.0 / K, beta_max=0.5, alpha_inc=2.0, alpha_dec=0.5,
-                inc_period=10)
+                inc_period=10, gamma=0.0)
+
+
+def default_gdm_params(K: int) -> dict:
+    """GDM parameters of the paper's experiments (Section 7.2)."""
+    return dict(beta_init=0.1, beta_min=1.0 / K, beta_max=0.2, alpha_inc=2.0, alpha_dec=0.5,
+                inc_period=10, gamma=0.9)
+
+
+def default_params(method: int, K: int) -> dict:
+    return default_gdm_params(K) if method == GDM else default_agd_params(K)
 
 
 class State:
-    """Resumable oracle run state: flows, AGD rates, iteration counter, z_prev."""
+    """Resumable oracle run state: flows, AGD/GDM rates, GDM velocities, iteration
+    counter, z_prev."""
 
     def __init__(self, inst, method=ESO, params=None):
         self.inst = inst
         self.method = method
-        self.params = default_agd_params(inst.K) if params is None else dict(params)
+        self.params = default_params(method, inst.K) if params is None else dict(params)
+        self.params.setdefault("gamma", 0.0)
         self.f = np.zeros((inst.m, inst.K))
+        self.v = np.zeros((inst.m, inst.K))
         self.beta = np.full(inst.m, self.params["beta_init"])
         self.t = 0
         self.z_prev = math.inf
@@ -193,7 +229,7 @@ class State:
         done = lib().orc_run(n, m, _p(args[0]), _p(args[1]), _p(args[2]), K, _p(args[3]),
                              _p(args[4]), _p(args[5]), int(self.method), C.byref(prm),
                              int(max_iter), float(eps_obj), float(z_target), _p(self.f),
-                             _p(self.beta), _p(t), _p(zp),
+                             _p(self.beta), _p(self.v), _p(t), _p(zp),
                              _p(zh) if record else None, _p(st))
         self.t = int(t[0])
         self.z_prev = float(zp[0])

@@ -42,6 +42,7 @@
 
 #define ORC_ESO 0
 #define ORC_AGD 1
+#define ORC_GDM 2
 /* parallel regions are used only when a loop has this much work */
 #define ORC_PAR_MIN 65536
 
@@ -273,16 +274,72 @@ int orc_agd_edge(int32_t K, const double *hi, const double *hj, const double *fe
     return accept;
 }
 
+/* One GDM arc step (Algorithm 4, inner loop): the step df_k = max(-f_k,
+ * beta phi_k) and its objective change are those of Algorithm 3; if the change
+ * is <= 0 the velocity becomes v' = gamma v + df and the flow max(0, f + v'),
+ * else flow and velocity are kept and beta decreases. The periodic increase of
+ * beta follows Algorithm 3's reading (after the decision, capped at beta_max).
+ * Writes the new flows to fout and velocities to vout; returns 1 if accepted. */
+int orc_gdm_edge(int32_t K, const double *hi, const double *hj, const double *fe, const double *ve,
+                 double F, double u, double psi, int64_t t, double *beta, double beta_min,
+                 double beta_max, double alpha_inc, double alpha_dec, int32_t inc_period,
+                 double gamma, double *fout, double *vout, double *dz_out)
+{
+    double b = *beta;
+    double sum_df = 0.0, quad = 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+        double g = hi[k] - hj[k];
+        double step = b * (g - psi);
+        double df = step > -fe[k] ? step : -fe[k];
+        fout[k] = df; /* hold the step until the decision */
+        sum_df += df;
+        quad += df * (df - g);
+    }
+    double before = F - u, after = F + sum_df - u;
+    double dcong;
+    if (before > 0.0 && after > 0.0)
+        dcong = sum_df * (before + 0.5 * sum_df);
+    else
+        dcong = 0.5 * ((after > 0.0 ? after * after : 0.0) - (before > 0.0 ? before * before : 0.0));
+    double dz = dcong + quad;
+    int accept = dz <= 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+        if (accept) {
+            double vn = gamma * ve[k] + fout[k];
+            double fn = fe[k] + vn;
+            vout[k] = vn;
+            fout[k] = fn > 0.0 ? fn : 0.0;
+        } else {
+            vout[k] = ve[k];
+            fout[k] = fe[k];
+        }
+    }
+    if (!accept) {
+        b = b * alpha_dec;
+        if (b < beta_min) b = beta_min;
+    }
+    if (inc_period > 0 && t % inc_period == 0) {
+        b = b * alpha_inc;
+        if (b > beta_max) b = beta_max;
+    }
+    *beta = b;
+    if (dz_out) *dz_out = dz;
+    return accept;
+}
+
 typedef struct {
     double beta_init, beta_min, beta_max, alpha_inc, alpha_dec;
     int32_t inc_period;
+    double gamma; /* momentum coefficient (Algorithm 4 only) */
 } orc_agd_params;
 
 /*
- * Algorithm 1 (method ORC_ESO) or Algorithm 3 (method ORC_AGD), resumable.
+ * Algorithm 1 (method ORC_ESO), Algorithm 3 (ORC_AGD) or Algorithm 4 (ORC_GDM),
+ * resumable.
  *
- * State in/out: f (m*K), beta (m, AGD only), *t (iteration counter),
- * *z_prev (previous objective, +inf at the start).
+ * State in/out: f (m*K), beta (m, AGD/GDM), v (m*K, GDM velocities; else may
+ * be NULL), *t (iteration counter), *z_prev (previous objective, +inf at the
+ * start; Algorithm 4 does not initialise it, read as +inf like Algorithms 1, 3).
  * Runs at most max_iter loop passes. Each pass computes heights, congestion and
  * z, records z into z_hist[pass] (if z_hist), applies the stop test
  * |z - z_prev| < eps_obj (eps_obj > 0) or z <= z_target (z_target > 0), and
@@ -292,7 +349,7 @@ typedef struct {
 int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col, const double *u,
                 int32_t K, const int32_t *s, const int32_t *t_sink, const double *d, int32_t method,
                 const orc_agd_params *prm, int64_t max_iter, double eps_obj, double z_target,
-                double *f, double *beta, int64_t *t, double *z_prev, double *z_hist,
+                double *f, double *beta, double *v, int64_t *t, double *z_prev, double *z_hist,
                 int32_t *stopped)
 {
     size_t nK = (size_t)n * K, mK = (size_t)m * K;
@@ -301,6 +358,7 @@ int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col
     double *F = (double *)malloc(sizeof(double) * (size_t)(m ? m : 1));
     double *psi = (double *)malloc(sizeof(double) * (size_t)(m ? m : 1));
     double *fnew = (double *)malloc(sizeof(double) * (mK ? mK : 1));
+    double *vnew = method == ORC_GDM ? (double *)malloc(sizeof(double) * (mK ? mK : 1)) : NULL;
     int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *tails = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
     orc_degrees(n, m, row_ptr, col, deg);
@@ -335,6 +393,10 @@ int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col
                 if (method == ORC_ESO) {
                     double ps, r;
                     orc_eso_edge(K, hi, hj, fe, u[e], fo, work, &ps, &r);
+                } else if (method == ORC_GDM) {
+                    orc_gdm_edge(K, hi, hj, fe, v + (size_t)e * K, F[e], u[e], psi[e], tt, &beta[e],
+                                 beta_min, prm->beta_max, prm->alpha_inc, prm->alpha_dec,
+                                 prm->inc_period, prm->gamma, fo, vnew + (size_t)e * K, NULL);
                 } else {
                     orc_agd_edge(K, hi, hj, fe, F[e], u[e], psi[e], tt, &beta[e], beta_min,
                                  prm->beta_max, prm->alpha_inc, prm->alpha_dec, prm->inc_period,
@@ -344,10 +406,11 @@ int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col
             free(work);
         }
         memcpy(f, fnew, sizeof(double) * mK);
+        if (vnew) memcpy(v, vnew, sizeof(double) * mK);
         *t = tt + 1;
         ++done;
     }
-    free(Delta); free(h); free(F); free(psi); free(fnew); free(deg); free(tails);
+    free(Delta); free(h); free(F); free(psi); free(fnew); free(vnew); free(deg); free(tails);
     return done;
 }
 

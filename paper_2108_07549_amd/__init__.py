@@ -25,14 +25,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdr.so")
 
-ESO, AGD = 0, 1
+ESO, AGD, GDM = 0, 1, 2
 FP64, FP32_BULK = 0, 1
 VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
 STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVICE",
           4: "PDR_ERR_STATE", 5: "PDR_ERR_NUMERIC"}
 
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
-           "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_z_log",
+           "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
            "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
            "pdr_tiling", "pdr_destroy", "pdr_last_error"]
 
@@ -46,11 +46,13 @@ class PdrError(RuntimeError):
 
 class AgdParams(C.Structure):
     _fields_ = [("beta_init", C.c_double), ("beta_min", C.c_double), ("beta_max", C.c_double),
-                ("alpha_inc", C.c_double), ("alpha_dec", C.c_double), ("inc_period", C.c_int32)]
+                ("alpha_inc", C.c_double), ("alpha_dec", C.c_double), ("inc_period", C.c_int32),
+                ("gamma", C.c_double)]
 
 
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("agd", AgdParams),
+                ("gdm", AgdParams),
                 ("z_feasible_tol", C.c_double), ("stream", C.c_void_p),
                 ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32),
                 ("graph_sweeps", C.c_int32), ("height_chunk", C.c_int32),
@@ -93,9 +95,10 @@ def lib():
         L.pdr_flows_device.argtypes = [P, P, i32]
         L.pdr_heights.argtypes = [P, P]
         L.pdr_learning_rates.argtypes = [P, P]
+        L.pdr_velocities.argtypes = [P, P]
         L.pdr_z_log.argtypes = [P, i64, i64, P]
         L.pdr_set_precision.argtypes = [P, i32]
-        L.pdr_set_state.argtypes = [P, P, P, i64, dbl]
+        L.pdr_set_state.argtypes = [P, P, P, P, i64, dbl]
         L.pdr_profile_sweeps.argtypes = [P, i64, P]
         L.pdr_measure_copy.argtypes = [i64, i32, P]
         L.pdr_tiling.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -156,9 +159,10 @@ def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, ve
     opt.cluster_size = int(cluster_size)
     opt.height_blocks = int(height_blocks)
     opt.height_unroll = int(height_unroll)
-    if agd:
+    if agd:  # overrides for the AGD or GDM parameters of the chosen method
+        target = opt.gdm if int(method) == GDM else opt.agd
         for k, v in agd.items():
-            setattr(opt.agd, k, v)
+            setattr(target, k, v)
     return opt
 
 
@@ -240,6 +244,11 @@ class Context:
         self._check(lib().pdr_learning_rates(self._h, _ptr(out)))
         return out
 
+    def velocities(self) -> np.ndarray:
+        out = np.empty((self.m, self.K), np.float64)
+        self._check(lib().pdr_velocities(self._h, _ptr(out)))
+        return out
+
     def z_log(self, first: int, count: int) -> np.ndarray:
         out = np.empty(max(int(count), 1), np.float64)
         self._check(lib().pdr_z_log(self._h, int(first), int(count), _ptr(out)))
@@ -248,11 +257,12 @@ class Context:
     def set_precision(self, precision: int):
         self._check(lib().pdr_set_precision(self._h, int(precision)))
 
-    def set_state(self, f, beta=None, t: int = 0, z_prev: float = float("inf")):
+    def set_state(self, f, beta=None, t: int = 0, z_prev: float = float("inf"), v=None):
         fa = np.ascontiguousarray(f, np.float64)
         ba = None if beta is None else np.ascontiguousarray(beta, np.float64)
+        va = None if v is None else np.ascontiguousarray(v, np.float64)
         self._check(lib().pdr_set_state(self._h, _ptr(fa), None if ba is None else _ptr(ba),
-                                        int(t), float(z_prev)))
+                                        None if va is None else _ptr(va), int(t), float(z_prev)))
 
     def profile_sweeps(self, sweeps: int) -> np.ndarray:
         """Run sweeps without a stop test; returns summed device ms of the

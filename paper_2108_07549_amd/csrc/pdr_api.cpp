@@ -64,8 +64,8 @@ struct pdr_ctx {
             *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr;
     double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
     // run state (device)
-    double *f64 = nullptr, *h64 = nullptr;
-    float *f32 = nullptr, *h32 = nullptr;
+    double *f64 = nullptr, *h64 = nullptr, *v64 = nullptr;
+    float *f32 = nullptr, *h32 = nullptr, *v32 = nullptr;
     double *Fsum = nullptr, *beta = nullptr, *zpart = nullptr, *maxpart = nullptr,
            *arcpart = nullptr, *resout = nullptr, *zlog = nullptr;
     int64_t nzpart = 0;
@@ -207,6 +207,7 @@ void set_height_chunk(pdr_ctx *c)
 }
 
 void *cur_f(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->f64 : (void *)c->f32; }
+void *cur_v(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->v64 : (void *)c->v32; }
 void *cur_h(pdr_ctx *c) { return c->precision == PDR_FP64 ? (void *)c->h64 : (void *)c->h32; }
 
 pdr_status ensure_buffers(pdr_ctx *c, int32_t precision)
@@ -229,6 +230,12 @@ pdr_status ensure_buffers(pdr_ctx *c, int32_t precision)
             if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (h)");
             PDR_CHECK(c, e);
         }
+    }
+    if (c->method == PDR_GDM) {  // velocities of Algorithm 4, in the storage precision
+        hipError_t e = precision == PDR_FP64 ? (c->v64 ? hipSuccess : dalloc(c, &c->v64, mK))
+                                             : (c->v32 ? hipSuccess : dalloc(c, &c->v32, mK));
+        if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (v)");
+        PDR_CHECK(c, e);
     }
     if (!c->h64) {  // FP64 heights: the FP64 sweep's h and every residual report
         hipError_t e = dalloc(c, &c->h64, nK);
@@ -324,7 +331,7 @@ void locality_order(int32_t n, const int32_t *rp, const int32_t *col,
 pdr::AgdParams agd_params(const pdr_ctx *c)
 {
     return pdr::AgdParams{c->beta_min, c->agd.beta_max, c->agd.alpha_inc, c->agd.alpha_dec,
-                          c->agd.inc_period};
+                          c->agd.inc_period, c->agd.gamma};
 }
 
 // Enqueue `count` passes (height, objective + stop test, arc update) on st.
@@ -339,7 +346,8 @@ hipError_t enqueue_passes(pdr_ctx *c, int64_t count, hipStream_t st)
         if (e == hipSuccess)
             e = c->method == PDR_ESO
                     ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, st)
-                    : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm, c->ctrl, st);
+                    : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm, c->ctrl,
+                                      c->method == PDR_GDM ? cur_v(c) : nullptr, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -403,6 +411,14 @@ void pdr_default_options(pdr_options *opt)
     opt->agd.alpha_inc = 2.0;
     opt->agd.alpha_dec = 0.5;
     opt->agd.inc_period = 10;
+    opt->agd.gamma = 0.0;
+    opt->gdm.beta_init = 0.1;
+    opt->gdm.beta_min = 0.0;  // 1/K
+    opt->gdm.beta_max = 0.2;
+    opt->gdm.alpha_inc = 2.0;
+    opt->gdm.alpha_dec = 0.5;
+    opt->gdm.inc_period = 10;
+    opt->gdm.gamma = 0.9;
     opt->z_feasible_tol = 1e-8;
     opt->stream = nullptr;
     opt->lanes_per_arc = 0;
@@ -475,24 +491,27 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
             return invalid("commodity endpoint has degree 0 (its height is undefined)");
     }
     // ---- options
-    if (opt.method != PDR_ESO && opt.method != PDR_AGD) return invalid("unknown method");
+    if (opt.method != PDR_ESO && opt.method != PDR_AGD && opt.method != PDR_GDM)
+        return invalid("unknown method");
     if (opt.precision != PDR_FP64 && opt.precision != PDR_FP32_BULK)
         return invalid("unknown precision");
-    if (opt.method == PDR_AGD) {
-        const pdr_agd_params &a = opt.agd;
+    if (opt.method == PDR_AGD || opt.method == PDR_GDM) {
+        const pdr_agd_params &a = opt.method == PDR_AGD ? opt.agd : opt.gdm;
         if (!(a.beta_init > 0) || !(a.beta_max > 0) || !(a.alpha_inc > 0) || !(a.alpha_dec > 0) ||
             !std::isfinite(a.beta_init) || !std::isfinite(a.beta_max) ||
             !std::isfinite(a.alpha_inc) || !std::isfinite(a.alpha_dec) ||
             !std::isfinite(a.beta_min) || a.inc_period < 0)
-            return invalid("invalid AGD parameters");
+            return invalid(opt.method == PDR_AGD ? "invalid AGD parameters" : "invalid GDM parameters");
+        if (opt.method == PDR_GDM && !(a.gamma >= 0.0 && a.gamma < 1.0))
+            return invalid("GDM momentum gamma must lie in [0, 1)");
     }
     if (!(opt.z_feasible_tol >= 0) || !std::isfinite(opt.z_feasible_tol))
         return invalid("z_feasible_tol must be finite and >= 0");
     if (opt.lanes_per_arc < 0 || opt.vec_per_lane < 0) return invalid("negative tiling request");
     if (opt.cluster_size < 0) return invalid("cluster_size must be >= 0");
     if (opt.height_unroll != 0 && opt.height_unroll != 1 && opt.height_unroll != 2 &&
-        opt.height_unroll != 4)
-        return invalid("height_unroll must be 0, 1, 2 or 4");
+        opt.height_unroll != 4 && opt.height_unroll != 8)
+        return invalid("height_unroll must be 0, 1, 2, 4 or 8");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..2048");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
@@ -506,8 +525,9 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->Kp = (int32_t)(K <= 64 ? (K + 3) / 4 * 4 : (K + 31) / 32 * 32);
     c->method = opt.method;
     c->precision = opt.precision;
-    c->agd = opt.agd;
-    c->beta_min = opt.agd.beta_min > 0 ? opt.agd.beta_min : 1.0 / K;
+    c->agd = opt.method == PDR_GDM ? opt.gdm : opt.agd;
+    if (opt.method != PDR_GDM) c->agd.gamma = 0.0;
+    c->beta_min = c->agd.beta_min > 0 ? c->agd.beta_min : 1.0 / K;
     c->z_feasible_tol = opt.z_feasible_tol;
     c->req_lanes = opt.lanes_per_arc;
     c->req_nv = opt.vec_per_lane;
@@ -540,7 +560,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     {
         const double w = c->precision == PDR_FP64 ? 8.0 : 4.0;
         const double mK = (double)m * c->Kp, nK = (double)n * c->Kp;
-        double need = mK * w + nK * w + nK * 8.0 * (c->precision == PDR_FP64 ? 0.0 : 1.0) +
+        double need = mK * w * (opt.method == PDR_GDM ? 2.0 : 1.0) + nK * w + nK * 8.0 * (c->precision == PDR_FP64 ? 0.0 : 1.0) +
                       8.0 * (6.0 * m + 4.0 * n + 4.0 * K) + 8.0 * (double)pdr::kZLogCap +
                       16.0 * (double)pdr::kHeightBlocksMax;
         size_t free_b = 0, total_b = 0;
@@ -654,14 +674,17 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_res, 8 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return oom_or_dev(e, "hipHostMalloc");
 
-    // ---- initial state: f = 0, beta = beta_init, t = 0, z_prev = +inf (Algorithms 1, 3)
+    // ---- initial state: f = 0, v = 0, beta = beta_init, t = 0, z_prev = +inf
+    // (Algorithms 1, 3, 4)
     const size_t mK = (size_t)m * c->Kp;
     void *f = cur_f(c);
     e = hipMemsetAsync(f, 0, mK * (c->precision == PDR_FP64 ? 8 : 4), c->stream);
+    if (e == hipSuccess && c->method == PDR_GDM)
+        e = hipMemsetAsync(cur_v(c), 0, mK * (c->precision == PDR_FP64 ? 8 : 4), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->Fsum, 0, (size_t)(m ? m : 1) * 8, c->stream);
     if (e != hipSuccess) return oom_or_dev(e, "hipMemsetAsync");
     {
-        std::vector<double> b(m > 0 ? m : 1, opt.agd.beta_init);
+        std::vector<double> b(m > 0 ? m : 1, c->agd.beta_init);
         e = hipMemcpyAsync(c->beta, b.data(), b.size() * 8, hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return oom_or_dev(e, "beta upload");
         std::memset(c->h_ctrl, 0, sizeof(Ctrl));
@@ -791,7 +814,8 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
                 err = c->method == PDR_ESO
                           ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream)
                           : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
-                                            c->ctrl, c->stream);
+                                            c->ctrl, c->method == PDR_GDM ? cur_v(c) : nullptr,
+                                            c->stream);
             if (err == hipSuccess) err = hipEventRecord(ev[q][2], c->stream);
         }
         if (err == hipSuccess) err = hipEventSynchronize(ev[nb - 1][2]);
@@ -908,6 +932,28 @@ pdr_status pdr_learning_rates(pdr_ctx *c, double *host_out)
     return PDR_OK;
 }
 
+pdr_status pdr_velocities(pdr_ctx *c, double *host_out)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (c->method != PDR_GDM) return fail(c, PDR_ERR_STATE, "velocities exist for PDR_GDM only");
+    if (!host_out) return fail(c, PDR_ERR_INVALID, "host_out is NULL");
+    if (c->m == 0) return PDR_OK;
+    const size_t K = c->K, Kp = c->Kp, m = c->m;
+    if (c->precision == PDR_FP64) {
+        PDR_CHECK(c, hipMemcpy2DAsync(host_out, K * 8, c->v64, Kp * 8, K * 8, m,
+                                      hipMemcpyDeviceToHost, c->stream));
+        PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(m * K);
+        PDR_CHECK(c, hipMemcpy2DAsync(tmp.data(), K * 4, c->v32, Kp * 4, K * 4, m,
+                                      hipMemcpyDeviceToHost, c->stream));
+        PDR_CHECK(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < m * K; ++q) host_out[q] = (double)tmp[q];
+    }
+    return PDR_OK;
+}
+
 pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
 {
     pdr_status st;
@@ -948,6 +994,12 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
         PDR_CHECK(c, pdr::launch_convert(c->f32, false, c->f64, true, mK, c->stream));
     else
         PDR_CHECK(c, pdr::launch_convert(c->f64, true, c->f32, false, mK, c->stream));
+    if (c->method == PDR_GDM) {
+        if (precision == PDR_FP64)
+            PDR_CHECK(c, pdr::launch_convert(c->v32, false, c->v64, true, mK, c->stream));
+        else
+            PDR_CHECK(c, pdr::launch_convert(c->v64, true, c->v32, false, mK, c->stream));
+    }
     c->precision = precision;
     c->tiling = tl;
     set_height_chunk(c);
@@ -957,8 +1009,8 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
     return PDR_OK;
 }
 
-pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, int64_t t,
-                         double z_prev)
+pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                         int64_t t, double z_prev)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -972,6 +1024,10 @@ pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, int64_
         for (int32_t e = 0; e < c->m; ++e)
             if (!(beta[e] > 0) || !std::isfinite(beta[e]))
                 return fail(c, PDR_ERR_INVALID, "learning rates must be finite and > 0");
+    const bool set_v = v && c->method == PDR_GDM;
+    if (set_v)
+        for (size_t q = 0; q < mK; ++q)
+            if (!std::isfinite(v[q])) return fail(c, PDR_ERR_INVALID, "velocities must be finite");
     if (c->m > 0) {
         double *staging = nullptr;
         hipError_t e = hipMalloc((void **)&staging, mK * 8);
@@ -984,6 +1040,12 @@ pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, int64_
             e = pdr::launch_rowsum(c->g, c->precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
                                    c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && set_v) {
+            e = hipMemcpyAsync(staging, v, mK * 8, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = pdr::launch_pad(c->g, staging, cur_v(c), c->precision == PDR_FP64, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        }
         (void)hipFree(staging);
         PDR_CHECK(c, e);
         if (beta)

@@ -52,6 +52,7 @@ struct DevGraph {
 struct AgdParams {
     double beta_min, beta_max, alpha_inc, alpha_dec;
     int32_t inc_period;
+    double gamma;  // momentum (GDM)
 };
 
 // Arc-kernel tiling: `lanes` lanes cooperate on one arc, each holding up to
@@ -73,8 +74,10 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
                                double *zpart, double *maxpart, hipStream_t st);
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
                       double *Fsum, const Ctrl *ctrl, hipStream_t st);
+// AGD arc update (Algorithm 3); with a velocity buffer vel, the GDM update
+// (Algorithm 4).
 hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
-                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl,
+                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl, void *vel,
                       hipStream_t st);
 hipError_t launch_rowsum(const DevGraph &g, bool fp64, Tiling tl, const void *f, double *Fsum,
                          hipStream_t st);

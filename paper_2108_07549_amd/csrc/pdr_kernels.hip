@@ -549,6 +549,101 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     }
 }
 
+// PDR-GDM arc update (Algorithm 4): the step df and its accept test are those
+// of Algorithm 3 (k_agd); an accepted arc takes v' = gamma v + df and
+// f' = max(0, f + v'), a rejected one keeps f and v and lowers beta. beta's
+// periodic increase is as in k_agd.
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restrict__ f,
+                                                          T *__restrict__ vel,
+                                                          const T *__restrict__ h,
+                                                          double *__restrict__ Fsum,
+                                                          double *__restrict__ beta,
+                                                          AgdParams prm,
+                                                          const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    constexpr int V = VecT<T>::N;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    int phase = 0;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    const int64_t e = g.aorder[slot];
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    const T *fe = f + e * Kp;
+    const T *ve = vel + e * Kp;
+    const T *hi = h + (int64_t)g.tails[e] * Kp;
+    const T *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+    const double F = Fsum[e];
+    const double psi = F > u ? F - u : 0.0;
+    const double b = beta[e];
+    const double gam = prm.gamma;
+
+    T nf[NV][V], nv[NV][V];  // the row's new flows and velocities if accepted
+    double red[3] = {0.0, 0.0, 0.0};  // sum df, sum df (df - g), sum of new flows
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            T a[V], bb[V], x[V], w0[V];
+            load_vec(fe + q * V, x);
+            load_vec(ve + q * V, w0);
+            load_vec(hi + q * V, a);
+            load_vec(hj + q * V, bb);
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const double gg = (double)(a[w] - bb[w]);
+                const double fx = (double)x[w];
+                const double step = b * (gg - psi);
+                const double df = step > -fx ? step : -fx;
+                const double vn = gam * (double)w0[w] + df;
+                const double fn = fx + vn;
+                nv[v][w] = (T)vn;
+                nf[v][w] = (T)(fn > 0.0 ? fn : 0.0);
+                red[0] += df;
+                red[1] += df * (df - gg);
+                red[2] += (double)nf[v][w];
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < V; ++w) nf[v][w] = nv[v][w] = (T)0;
+        }
+    }
+    group_sum<L, 3>(red, lds, phase);
+    const double before = F - u, after = F + red[0] - u;
+    const double dcong = (before > 0.0 && after > 0.0)
+                             ? red[0] * (before + 0.5 * red[0])
+                             : 0.5 * ((after > 0.0 ? after * after : 0.0) -
+                                      (before > 0.0 ? before * before : 0.0));
+    const bool accept = dcong + red[1] <= 0.0;
+    if (accept) {
+        T *fo = f + e * Kp;
+        T *vo = vel + e * Kp;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int q = v * L + lane;
+            if (q < nvec) {
+                store_vec(fo + q * V, nf[v]);
+                store_vec(vo + q * V, nv[v]);
+            }
+        }
+    }
+    if (lane == 0) {
+        double nb = b;
+        if (!accept) nb = fmax(prm.beta_min, nb * prm.alpha_dec);
+        if (prm.inc_period > 0 && (ctrl->t_pass % prm.inc_period) == 0)
+            nb = fmin(prm.beta_max, nb * prm.alpha_inc);
+        beta[e] = nb;
+        if (accept) Fsum[e] = red[2];
+    }
+}
+
 // Fsum[e] = sum_k f[e, k] with the same lane layout and reduction tree as the
 // arc kernels (so a restored state continues bit for bit).
 template <typename T, int L, int NV>
@@ -753,7 +848,7 @@ hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t
     return hipGetLastError();
 }
 
-#define PDR_HEIGHT_UNROLL(X) X(1) X(2) X(4)
+#define PDR_HEIGHT_UNROLL(X) X(1) X(2) X(4) X(8)
 
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
                          const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
@@ -844,14 +939,21 @@ hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
 }
 
 hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
-                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl, hipStream_t st)
+                      double *Fsum, double *beta, AgdParams prm, const Ctrl *ctrl, void *vel,
+                      hipStream_t st)
 {
     if (g.m == 0) return hipSuccess;
 #define PDR_AGD_CASE(L_, NV_)                                                                  \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
         const unsigned nb = arc_blocks(g.m, L_);                                               \
         constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
-        if (fp64)                                                                              \
+        if (vel && fp64)                                                                       \
+            k_gdm<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (double *)vel,           \
+                                                      (const double *)h, Fsum, beta, prm, ctrl); \
+        else if (vel)                                                                          \
+            k_gdm<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (float *)vel,              \
+                                                     (const float *)h, Fsum, beta, prm, ctrl); \
+        else if (fp64)                                                                         \
             k_agd<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h, Fsum, \
                                                       beta, prm, ctrl);                        \
         else                                                                                   \

@@ -165,11 +165,16 @@ def edge_objective(F, dfs, hi, hj, u) -> Fr:
 
 
 def exact_pdr(ex: ExactInstance, method: str, T: int, params=None):
-    """T passes of Algorithm 1 ('eso') or Algorithm 3 ('agd') from f = 0.
+    """T passes of Algorithm 1 ('eso'), Algorithm 3 ('agd') or Algorithm 4 ('gdm')
+    from f = 0 (and zero velocities).
 
     Returns (f, list of z values before each update)."""
     K, m = ex.K, ex.m
     f = [[ZERO] * K for _ in range(m)]
+    vel = [[ZERO] * K for _ in range(m)]
+    if params is None and method == "gdm":
+        params = dict(beta_init=Fr(1, 10), beta_min=Fr(1, K), beta_max=Fr(1, 5),
+                      alpha_inc=Fr(2), alpha_dec=Fr(1, 2), inc_period=10, gamma=Fr(9, 10))
     p = params or dict(beta_init=Fr(1, 4), beta_min=Fr(1, K), beta_max=Fr(1, 2),
                        alpha_inc=Fr(2), alpha_dec=Fr(1, 2), inc_period=10)
     beta = [fr(p["beta_init"])] * m
@@ -191,7 +196,11 @@ def exact_pdr(ex: ExactInstance, method: str, T: int, params=None):
                 dz = (edge_objective(F, dfs, h[i], h[j], ex.u[e])
                       - edge_objective(F, [ZERO] * K, h[i], h[j], ex.u[e]))
                 b = beta[e]
-                if dz <= 0:
+                if dz <= 0 and method == "gdm":
+                    g = fr(p["gamma"])
+                    vel[e] = [g * vel[e][k] + dfs[k] for k in range(K)]
+                    fn.append([max(ZERO, f[e][k] + vel[e][k]) for k in range(K)])
+                elif dz <= 0:
                     fn.append([f[e][k] + dfs[k] for k in range(K)])
                 else:
                     fn.append(list(f[e]))

@@ -35,6 +35,9 @@ def test_default_options_are_the_papers_settings():
     a = o.agd
     assert (a.beta_init, a.beta_min, a.beta_max, a.alpha_inc, a.alpha_dec, a.inc_period) == \
         (0.25, 0.0, 0.5, 2.0, 0.5, 10)
+    g = o.gdm  # Section 7.2's GDM settings; beta_min 0 selects 1/K
+    assert (g.beta_init, g.beta_min, g.beta_max, g.alpha_inc, g.alpha_dec, g.inc_period,
+            g.gamma) == (0.1, 0.0, 0.2, 2.0, 0.5, 10, 0.9)
     assert o.z_feasible_tol == 1e-8 and not o.stream
 
 
@@ -83,6 +86,9 @@ def test_init_rejects_isolated_commodity_endpoint():
     (dict(precision=3), "unknown precision"),
     (dict(method=pdr.AGD, agd=dict(beta_init=0.0)), "AGD parameters"),
     (dict(method=pdr.AGD, agd=dict(alpha_dec=float("nan"))), "AGD parameters"),
+    (dict(method=pdr.GDM, agd=dict(beta_max=0.0)), "GDM parameters"),
+    (dict(method=pdr.GDM, agd=dict(gamma=1.0)), "gamma"),
+    (dict(method=pdr.GDM, agd=dict(gamma=-0.1)), "gamma"),
     (dict(z_feasible_tol=-1.0), "z_feasible_tol"),
     (dict(lanes_per_arc=3), "tiling"),
     (dict(lanes_per_arc=1, vec_per_lane=1), "tiling"),  # K=100 needs more than 1 x 1 vectors

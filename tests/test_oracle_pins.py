@@ -36,7 +36,9 @@ def read_golden(name):
                 continue
             parts = [p.strip() for p in line.split("|")]
             rows[parts[0]] = dict(d=Fr(parts[1]), u=Fr(parts[2]), K=int(parts[3]), method=parts[4],
-                                  flows=[Fr(x) for x in parts[5].split()])
+                                  flows=[Fr(x) for x in parts[5].split()],
+                                  flows1=[Fr(x) for x in parts[6].split()] if len(parts) > 6
+                                  else None)
     return rows
 
 
@@ -195,18 +197,31 @@ def test_potential_difference_is_negative_gradient():
 
 
 # ------------------------------------------------------------------ P5: worked closed forms
-@pytest.mark.parametrize("name", ["eso_infeasible", "eso_feasible", "agd_feasible", "agd_reject"])
+@pytest.mark.parametrize("name", ["eso_infeasible", "eso_feasible", "agd_feasible", "agd_reject",
+                                  "gdm_feasible"])
 def test_two_vertex_worked_examples(name):
     """P5: the oracle reproduces the hand-derived trajectories in tests/golden/two_vertex.txt."""
     g = read_golden("two_vertex.txt")[name]
     inst = two_vertex(float(g["d"]), float(g["u"]), g["K"])
-    method = oracle.ESO if g["method"] == "eso" else oracle.AGD
+    method = {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM}[g["method"]]
     st = oracle.State(inst, method)
     for step, expect in enumerate(g["flows"]):
         st.run(1)
         e0 = 0  # arc 0->1 is first in CSR order
         assert np.allclose(st.f[e0], float(expect), rtol=0, atol=1e-13 * float(g["d"])), (name, step)
-        assert np.all(st.f[1] == 0.0)
+        expect1 = 0.0 if g["flows1"] is None else float(g["flows1"][step])
+        assert np.allclose(st.f[1], expect1, rtol=0, atol=1e-13 * float(g["d"])), (name, step)
+
+
+def test_gdm_without_momentum_is_agd():
+    """Algorithm 4 with gamma = 0 is Algorithm 3 (the step never drives f below 0,
+    so max(0, f + df) = f + df)."""
+    inst = recipe_small("knn", 30, 9, seed=6, u_range=(1, 6), d_range=(1, 6))
+    prm = oracle.default_agd_params(inst.K)
+    a, za = oracle.run(inst, oracle.AGD, 150, params=prm)
+    b, zb = oracle.run(inst, oracle.GDM, 150, params=dict(prm, gamma=0.0))
+    assert np.array_equal(a.f, b.f) and np.array_equal(a.beta, b.beta)
+    assert np.array_equal(za, zb)
 
 
 def test_two_vertex_fixed_point_and_farkas_gap():
@@ -253,14 +268,14 @@ def test_agd_objective_change_is_exact_subproblem_difference():
 
 
 # ------------------------------------------------------------------ P4: exact sweeps
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ["eso", "agd", "gdm"])
 def test_oracle_matches_exact_rational_sweeps(grid4, method):
     """P4: 60 sweeps in exact rationals (independent code: threshold QP, in/out arc
     lists, direct subproblem differences) match the FP64 oracle to 1e-12 max(u)."""
     inst = grid4
     ex = ExactInstance.from_instance(inst)
     f_ex, z_ex = exact_pdr(ex, method, 60)
-    st, zs = oracle.run(inst, oracle.ESO if method == "eso" else oracle.AGD, 60)
+    st, zs = oracle.run(inst, {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM}[method], 60)
     f_ex = np.array([[float(x) for x in row] for row in f_ex])
     tol = 1e-12 * float(np.max(inst.u))
     assert np.max(np.abs(st.f - f_ex)) <= tol
@@ -372,7 +387,7 @@ def test_verdict_matches_maxflow_single_commodity():
 # ------------------------------------------------------------------ P10/P11/P12
 def test_scale_covariance_bitwise(grid4):
     """P10: (u, d) -> (4u, 4d) scales every iterate by 4 exactly (powers of two)."""
-    for method in (oracle.ESO, oracle.AGD):
+    for method in (oracle.ESO, oracle.AGD, oracle.GDM):
         a, za = oracle.run(grid4, method, 50)
         b, zb = oracle.run(grid4.scaled(4.0), method, 50)
         assert np.array_equal(b.f, 4.0 * a.f)
@@ -418,12 +433,13 @@ def test_zero_commodity_padding_is_exact(grid4):
 # ------------------------------------------------------------------ run semantics
 def test_resume_equals_single_run(grid4):
     """T sweeps then T' sweeps equal T + T' sweeps bitwise (state: f, beta, t, z_prev)."""
-    for method in (oracle.ESO, oracle.AGD):
+    for method in (oracle.ESO, oracle.AGD, oracle.GDM):
         a, _ = oracle.run(grid4, method, 37)
         b = oracle.State(grid4, method)
         b.run(20)
         b.run(17)
         assert np.array_equal(a.f, b.f) and np.array_equal(a.beta, b.beta) and a.t == b.t
+        assert np.array_equal(a.v, b.v)
 
 
 def test_stop_rule_is_checked_before_update(grid4):

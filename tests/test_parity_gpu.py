@@ -17,7 +17,9 @@ from gen.instance import MissingLoadFactor, load_instance, recipe_grid4_k8, reci
 
 pytestmark = pytest.mark.gpu
 
-METHODS = {"eso": (pdr.ESO, oracle.ESO), "agd": (pdr.AGD, oracle.AGD)}
+METHODS = {"eso": (pdr.ESO, oracle.ESO), "agd": (pdr.AGD, oracle.AGD),
+           "gdm": (pdr.GDM, oracle.GDM)}
+ALL = list(METHODS)
 
 
 def say(*a):
@@ -47,12 +49,15 @@ def run_pair(inst, method_name, T, **kw):
         res = c.residual()
         hg = c.heights()
         bg = c.learning_rates()
+        vg = c.velocities() if gm == pdr.GDM else None
     st, zo = oracle.run(inst, om, T)
-    return dict(fg=fg, zg=zg, res=res, hg=hg, bg=bg, st=st, zo=zo)
+    if vg is not None:  # momentum state: same tolerance as the flows
+        assert np.max(np.abs(vg - st.v)) <= flow_tol(inst)
+    return dict(fg=fg, zg=zg, res=res, hg=hg, bg=bg, vg=vg, st=st, zo=zo)
 
 
 # ------------------------------------------------------------------ grid 4x4, K=8, 500 sweeps
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_grid4_k8_500_sweeps(method):
     inst = recipe_grid4_k8()
     r = run_pair(inst, method, 500)
@@ -64,7 +69,7 @@ def test_grid4_k8_500_sweeps(method):
     _, ho = oracle.excess(inst, r["st"].f)
     assert np.max(np.abs(r["hg"] - ho)) <= tol
     assert r["res"]["sweeps_done"] == 500 and r["res"]["evaluations"] == 500
-    if method == "agd":
+    if method != "eso":
         assert np.array_equal(r["bg"], r["st"].beta)
 
 
@@ -94,7 +99,7 @@ def _tilings(nvec):
 
 
 @pytest.mark.parametrize("precision", [pdr.FP64, pdr.FP32_BULK])
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_every_tiling_gives_the_same_iterates(method, precision):
     """Every supported lanes-per-arc x vectors-per-lane layout runs the same
     sweep: FP64 results match the oracle; FP32 layouts agree with each other."""
@@ -122,7 +127,7 @@ def test_every_tiling_gives_the_same_iterates(method, precision):
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 5, 31, 33, 63, 65, 127, 129, 255, 257, 1000, 1025, 3001])
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_ragged_commodity_counts(method, K):
     """Row lengths that leave ragged vectors, groups and padding."""
     side = 3 if K <= 72 else 8  # K distinct ordered (s, t) pairs must exist
@@ -149,7 +154,7 @@ def test_two_vertex_infeasible_closed_form():
     assert res["verdict"] == "infeasible"
 
 
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_degenerate_instances(method):
     gm, om = METHODS[method]
     cases = {
@@ -173,7 +178,7 @@ def test_degenerate_instances(method):
     assert np.all(zd["fg"] == 0.0) and np.all(zd["zg"] == 0.0)
 
 
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_stop_rules_match_the_oracle(method):
     gm, om = METHODS[method]
     inst = recipe_grid4_k8()
@@ -195,25 +200,30 @@ def test_stop_rules_match_the_oracle(method):
             assert c.residual()["sweeps_done"] == t0
 
 
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_resume_and_determinism_are_bitwise(method):
     gm, _ = METHODS[method]
     inst = recipe_small("knn", 50, 70, seed=3, u_range=(2, 8), d_range=(1, 6))
+    gdm = gm == pdr.GDM
     with ctx_for(inst, gm) as a:
         a.sweep(37)
         fa, ba = a.flows(), a.learning_rates()
+        va = a.velocities() if gdm else None
     with ctx_for(inst, gm) as b:
         b.sweep(37)
         assert np.array_equal(b.flows(), fa)
     with ctx_for(inst, gm) as c:
         c.sweep(20)
         f20, b20 = c.flows(), c.learning_rates()
+        v20 = c.velocities() if gdm else None
         z_prev = c.z_log(19, 1)[0]
     with ctx_for(inst, gm) as d:
-        d.set_state(f20, b20, t=20, z_prev=z_prev)
+        d.set_state(f20, b20, t=20, z_prev=z_prev, v=v20)
         d.sweep(17)
         assert np.array_equal(d.flows(), fa)
         assert np.array_equal(d.learning_rates(), ba)
+        if gdm:
+            assert np.array_equal(d.velocities(), va)
 
 
 TORCH_INTEROP = r"""
@@ -284,7 +294,7 @@ def test_oversize_instance_is_out_of_memory_before_allocation():
 
 
 # ------------------------------------------------------------------ FP32 bulk + FP64 polish
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_fp32_bulk_error_and_fp64_polish(method):
     """FP32 storage: stated error against the FP64 oracle; then the FP64 polish
     (exact widening of the flows) continues to z <= 1e-8."""
@@ -308,7 +318,7 @@ def test_fp32_bulk_error_and_fp64_polish(method):
 
 
 # ------------------------------------------------------------------ benchmark-size instances
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_knn2500_k1000_200_sweeps(method):
     inst = load_instance("knn2500_k1000")
     r = run_pair(inst, method, 200)
@@ -318,7 +328,7 @@ def test_knn2500_k1000_200_sweeps(method):
     assert r["res"]["verdict"] == rep["verdict"]
 
 
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_grid100_k10000_3_sweeps(method):
     """Full size of the benchmark workload, the launch configuration the
     benchmark times, all outputs compared."""
@@ -332,7 +342,7 @@ def test_grid100_k10000_3_sweeps(method):
 
 
 # ------------------------------------------------------------------ graph replays, solve
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_graph_replays_match_direct_launches(method):
     """Sweeps replayed from a captured HIP graph equal directly launched sweeps,
     replay after replay, with host reads and synchronisations between replays."""
@@ -352,7 +362,7 @@ def test_graph_replays_match_direct_launches(method):
     assert np.max(np.abs(fg - oracle.run(inst, om, 40)[0].f)) <= flow_tol(inst)
 
 
-@pytest.mark.parametrize("method", ["eso", "agd"])
+@pytest.mark.parametrize("method", ALL)
 def test_solve_fp64_and_fp32_polish_reach_target(method):
     gm, om = METHODS[method]
     inst = recipe_small("grid", 5, 20, seed=3, u_range=(5, 20), d_range=(1, 5))
