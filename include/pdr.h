@@ -83,7 +83,7 @@ typedef struct {
     int32_t cluster_size;  /* vertices per locality cluster of the visiting order:
                               0 = automatic (64), 1 = the caller's vertex order */
     int32_t height_blocks; /* blocks of the grid-stride height kernel: 0 = automatic,
-                              else 1..2048 (tuning) */
+                              else 1..8192 (tuning) */
     int32_t height_unroll; /* incident rows each height-kernel thread loads before
                               summing: 0 = automatic, 1, 2, 4 or 8 (tuning) */
 } pdr_options;

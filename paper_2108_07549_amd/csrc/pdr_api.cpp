@@ -131,22 +131,28 @@ int pow2ceil(int64_t x)
 
 int vec_of(int32_t precision) { return precision == PDR_FP64 ? 2 : 4; }
 
-Tiling auto_tiling(int32_t Kp, int32_t precision)
+// Fewest register vectors per lane (a supported count) that cover nvec with L lanes;
+// 0 if none does.
+int cover_nv(int64_t nvec, int L)
+{
+    const int need = (int)((nvec + L - 1) / L);
+    for (int cand = need < 1 ? 1 : need; cand <= kMaxNv; ++cand)
+        if (pdr::tiling_supported(L, cand)) return cand;
+    return 0;
+}
+
+Tiling auto_tiling(int32_t Kp, int32_t precision, int32_t method)
 {
     const int64_t nvec = Kp / vec_of(precision);
     // about five register vectors per lane: long rows get many lanes, and
     // the blocks stay small enough that several arcs share a CU
     int L = pow2ceil((nvec + 4) / 5);
     if (L > kMaxLanes) L = kMaxLanes;
-    const int need = (int)((nvec + L - 1) / L);
-    // the fewest register vectors per lane that cover the row
-    int nv = pow2ceil(need);
-    for (int cand = need; cand <= nv; ++cand)
-        if (pdr::tiling_supported(L, cand)) {
-            nv = cand;
-            break;
-        }
-    if (nv < 1) nv = 1;
+    // the gradient steps reduce once per arc (no threshold passes): they run
+    // best with at most 512 lanes and more vectors per lane
+    if (method != PDR_ESO && L > 512 && cover_nv(nvec, 512) > 0) L = 512;
+    int nv = cover_nv(nvec, L);
+    if (nv < 1) nv = pow2ceil((nvec + L - 1) / L);
     return Tiling{L, nv};
 }
 
@@ -158,7 +164,7 @@ bool tiling_covers(Tiling tl, int32_t Kp, int32_t precision)
 
 pdr_status choose_tiling(pdr_ctx *c, int32_t precision, Tiling *out)
 {
-    Tiling tl = auto_tiling(c->Kp, precision);
+    Tiling tl = auto_tiling(c->Kp, precision, c->method);
     if (c->req_lanes > 0 || c->req_nv > 0) {
         tl.lanes = c->req_lanes > 0 ? c->req_lanes : tl.lanes;
         tl.nv = c->req_nv > 0 ? c->req_nv : pow2ceil((c->Kp / vec_of(precision) + tl.lanes - 1) /
@@ -513,7 +519,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
         opt.height_unroll != 4 && opt.height_unroll != 8)
         return invalid("height_unroll must be 0, 1, 2, 4 or 8");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
-        return invalid("height_blocks must be 0 or 1..2048");
+        return invalid("height_blocks must be 0 or 1..8192");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
         (opt.height_chunk & (opt.height_chunk - 1)) != 0)
         return invalid("height_chunk must be 0 or a power of two up to 256");

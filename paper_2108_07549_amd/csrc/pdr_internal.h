@@ -25,7 +25,7 @@ struct Ctrl {
 constexpr int64_t kZLogCap = int64_t(1) << 20;
 // The height kernel is grid-stride with at most this many blocks (8 per CU),
 // which also bounds the number of objective partials.
-constexpr int64_t kHeightBlocksMax = 2048;
+constexpr int64_t kHeightBlocksMax = 8192;
 
 // Graph and instance arrays in device memory.
 struct DevGraph {

@@ -60,6 +60,56 @@ __device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&v)[VecT<T
     }
 }
 
+// Streaming variants for data touched once per kernel (an arc's own flow
+// row): non-temporal accesses keep such rows from evicting the height rows
+// that neighbouring arcs re-read from L2.
+#ifndef PDR_ARC_NT
+#define PDR_ARC_NT 1
+#endif
+#ifndef PDR_HEIGHT_NT
+#define PDR_HEIGHT_NT 1
+#endif
+typedef double pdr_d2 __attribute__((ext_vector_type(2)));
+typedef float pdr_f4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename T>
+__device__ __forceinline__ void load_vec_s(const T *__restrict__ p, T (&v)[VecT<T>::N])
+{
+    if constexpr (!NT) {
+        load_vec(p, v);
+    } else if constexpr (sizeof(T) == 8) {
+        const pdr_d2 x = __builtin_nontemporal_load(reinterpret_cast<const pdr_d2 *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        const pdr_f4 x = __builtin_nontemporal_load(reinterpret_cast<const pdr_f4 *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void store_vec_s(T *__restrict__ p, const T (&v)[VecT<T>::N])
+{
+    if constexpr (!NT) {
+        store_vec(p, v);
+    } else if constexpr (sizeof(T) == 8) {
+        pdr_d2 x;
+        x.x = v[0];
+        x.y = v[1];
+        __builtin_nontemporal_store(x, reinterpret_cast<pdr_d2 *>(p));
+    } else {
+        pdr_f4 x;
+        x.x = v[0];
+        x.y = v[1];
+        x.z = v[2];
+        x.w = v[3];
+        __builtin_nontemporal_store(x, reinterpret_cast<pdr_f4 *>(p));
+    }
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs. Remap so that each XCD
 // works through one contiguous range of logical blocks; consecutive arcs share
 // their tail row of h, which then stays in that XCD's L2.
@@ -315,7 +365,7 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
             for (int w = 0; w < V; w += 2)
                 *reinterpret_cast<double2 *>(dst + w) = make_double2(hd[w], hd[w + 1]);
         } else {
-            store_vec(h + (int64_t)i * Kp + k0, hv);
+            store_vec_s<PDR_HEIGHT_NT>(h + (int64_t)i * Kp + k0, hv);
         }
     }
     double ps = 0.0;
@@ -395,7 +445,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], b[V], x[V];
-            load_vec(fe + q * V, x);
+            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, b);
 #pragma unroll
@@ -452,7 +502,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
                 o[w] = (T)(val > 0.0 ? val : 0.0);
                 fs[0] += (double)o[w];
             }
-            store_vec(fo + q * V, o);
+            store_vec_s<PDR_ARC_NT>(fo + q * V, o);
         }
     }
     group_sum<L, 1>(fs, lds, phase);
@@ -501,7 +551,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], bb[V], x[V];
-            load_vec(fe + q * V, x);
+            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, bb);
 #pragma unroll
@@ -536,7 +586,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int q = v * L + lane;
-            if (q < nvec) store_vec(fo + q * V, cand[v]);
+            if (q < nvec) store_vec_s<PDR_ARC_NT>(fo + q * V, cand[v]);
         }
     }
     if (lane == 0) {
@@ -592,8 +642,8 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restri
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], bb[V], x[V], w0[V];
-            load_vec(fe + q * V, x);
-            load_vec(ve + q * V, w0);
+            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
+            load_vec_s<PDR_ARC_NT>(ve + q * V, w0);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, bb);
 #pragma unroll
@@ -629,8 +679,8 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restri
         for (int v = 0; v < NV; ++v) {
             const int q = v * L + lane;
             if (q < nvec) {
-                store_vec(fo + q * V, nf[v]);
-                store_vec(vo + q * V, nv[v]);
+                store_vec_s<PDR_ARC_NT>(fo + q * V, nf[v]);
+                store_vec_s<PDR_ARC_NT>(vo + q * V, nv[v]);
             }
         }
     }
@@ -668,7 +718,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
         const int q = v * L + lane;
         if (q < nvec) {
             T x[V];
-            load_vec(fe + q * V, x);
+            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
 #pragma unroll
             for (int w = 0; w < V; ++w) fs[0] += (double)x[w];
         }
