@@ -856,22 +856,29 @@ __global__ __launch_bounds__(256) void k_pad(const double *__restrict__ src, D *
     }
 }
 
-// Plain 16-byte copy, the reference for what HBM delivers to a streaming kernel.
-// Each thread moves four independent 16-byte vectors per step.
+// Plain 16-byte copy, the reference for what HBM delivers to a streaming
+// kernel: each block copies contiguous tiles of 4 x 256 vectors with
+// non-temporal loads and stores (the fastest of the simple copy shapes on
+// this GPU).
 __global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src,
                                               double2 *__restrict__ dst, int64_t count)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; q + 3 * stride < count; q += 4 * stride) {
-        const double2 a = src[q], b = src[q + stride], c = src[q + 2 * stride],
-                      d = src[q + 3 * stride];
-        dst[q] = a;
-        dst[q + stride] = b;
-        dst[q + 2 * stride] = c;
-        dst[q + 3 * stride] = d;
+    constexpr int U = 4;
+    const int64_t tile = 256 * U;
+    const int64_t ntiles = count / tile;
+    const pdr_d2 *s = reinterpret_cast<const pdr_d2 *>(src);
+    pdr_d2 *d = reinterpret_cast<pdr_d2 *>(dst);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * tile + threadIdx.x;
+        pdr_d2 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = __builtin_nontemporal_load(s + base + u * 256);
+#pragma unroll
+        for (int u = 0; u < U; ++u) __builtin_nontemporal_store(x[u], d + base + u * 256);
     }
-    for (; q < count; q += stride) dst[q] = src[q];
+    for (int64_t q = ntiles * tile + (int64_t)blockIdx.x * 256 + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * 256)
+        dst[q] = src[q];
 }
 
 // ----------------------------------------------------------------- launchers
@@ -1054,7 +1061,7 @@ hipError_t launch_resid(const DevGraph &g, bool fp64, const void *f, const doubl
 
 hipError_t launch_copy(const void *src, void *dst, int64_t count16, hipStream_t st)
 {
-    k_copy<<<grid_for(count16, 4096), 256, 0, st>>>((const double2 *)src, (double2 *)dst, count16);
+    k_copy<<<grid_for(count16, 16384), 256, 0, st>>>((const double2 *)src, (double2 *)dst, count16);
     return hipGetLastError();
 }
 
