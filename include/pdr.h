@@ -86,6 +86,8 @@ typedef struct {
                               else 1..8192 (tuning) */
     int32_t height_unroll; /* incident rows each height-kernel thread loads before
                               summing: 0 = automatic, 1, 2, 4 or 8 (tuning) */
+    int32_t z_log_capacity; /* objective evaluations kept by pdr_z_log: 0 = 2^20,
+                               else a power of two up to 2^20 */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */
@@ -186,12 +188,14 @@ pdr_status pdr_velocities(pdr_ctx *ctx, double *host_out);
 
 /* Copy z log entries [first, first + count) to host_out (synchronizes).
  * Entry q is the objective of the q-th evaluation since init. The log keeps
- * the last 2^20 evaluations; older entries return PDR_ERR_INVALID. */
+ * the last z_log_capacity (default 2^20) evaluations; older entries return
+ * PDR_ERR_INVALID. */
 pdr_status pdr_z_log(pdr_ctx *ctx, int64_t first, int64_t count, double *host_out);
 
 /* Switch the storage precision. FP32_BULK -> FP64 widens the current flows
  * exactly (the FP64 "polish" phase); FP64 -> FP32_BULK rounds them. The
- * iteration counter, z_prev and learning rates are kept. */
+ * iteration counter, z_prev and learning rates are kept. A batch member
+ * returns PDR_ERR_STATE: its batch switches with pdr_batch_set_precision. */
 pdr_status pdr_set_precision(pdr_ctx *ctx, int32_t precision);
 
 /* Replace the run state: flows f[m*K] (FP64, >= 0, finite), AGD/GDM rates
@@ -210,7 +214,7 @@ pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
 
 /* Measurement: the HBM bandwidth of a plain copy on the current device.
  * Copies `bytes` (rounded down to 16) between two freshly allocated device
- * buffers `iters` times with a 16-byte-vector grid-stride kernel (k_copy) and
+ * buffers `iters` times with a 16-byte-vector tiled copy kernel (k_copy) and
  * writes the mean read+write bandwidth in GB/s (2 * bytes per copy / time)
  * to *gbps. The buffers are freed before return. Context-free. */
 pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps);
@@ -220,12 +224,96 @@ pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps);
 pdr_status pdr_tiling(const pdr_ctx *ctx, int32_t *lanes_per_arc, int32_t *vec_per_lane,
                       int32_t *Kp);
 
-/* Release the context and all its device memory. NULL is ignored. */
+/* Release the context and all its device memory. NULL is ignored, and so is a
+ * batch member (pdr_batch_destroy releases members). */
 void pdr_destroy(pdr_ctx *ctx);
 
 /* Text of the last failure of ctx, or of the calling thread's last failed
  * pdr_init when ctx is NULL. Never NULL. */
 const char *pdr_last_error(const pdr_ctx *ctx);
+
+/* ---------------------------------------------------------------- batches
+ * A batch sweeps many independent instances at once: every pass of
+ * Algorithm 1, 3 or 4 runs for all of them in a handful of launches (one
+ * height launch, one objective launch, one arc launch per tiling bucket),
+ * captured in HIP graphs. Each instance keeps its own stop test, counters and
+ * verdict; its results are read through its member context. */
+typedef struct pdr_batch pdr_batch;
+
+/* One instance of Section 1 (same arrays and rules as pdr_init). */
+typedef struct {
+    int32_t n, m;
+    const int64_t *row_ptr; /* n+1 */
+    const int32_t *col;     /* m heads */
+    const double *u;        /* m capacities */
+    int32_t K;
+    const int32_t *s, *t;   /* K */
+    const double *d;        /* K */
+} pdr_instance;
+
+/* A tiling bucket: the members whose arc kernels share one tiling. */
+typedef struct {
+    int32_t lanes_per_arc, vec_per_lane;
+    int32_t instances;      /* members in the bucket */
+    int32_t max_K;          /* largest commodity count among them */
+    int64_t arcs;           /* their arcs in total */
+    double ms;              /* arc-kernel time measured by the last pdr_batch_tune
+                               (0 before tuning) */
+} pdr_bucket_info;
+
+/* Create a batch of B instances (deep copies; the caller keeps the arrays).
+ * opt (NULL: defaults) applies to every member: method, precision, AGD/GDM
+ * parameters, stream (NULL: the batch creates one; all members share it),
+ * graph_sweeps (passes per captured batch graph). Members keep 4096 z log
+ * entries unless opt->z_log_capacity says otherwise. A failing instance fails
+ * the whole call (status of that instance; pdr_batch_last_error(NULL) names it);
+ * *out is NULL then. */
+pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
+                          const pdr_options *opt);
+
+/* Up to max_sweeps passes for every member, each stopping on its own test
+ * (eps_obj, z_target as in pdr_sweep). Stopped members skip the remaining
+ * passes; the call returns early once every member has stopped.
+ * Asynchronous on the batch stream. */
+pdr_status pdr_batch_sweep(pdr_batch *batch, int64_t max_sweeps, double eps_obj,
+                           double z_target);
+
+/* The context of member `index` (0 <= index < B), for pdr_residual,
+ * pdr_flows, pdr_z_log, pdr_learning_rates, pdr_velocities, pdr_set_state and
+ * the other per-instance calls. Owned by the batch: pdr_destroy ignores it. */
+pdr_status pdr_batch_member(pdr_batch *batch, int32_t index, pdr_ctx **ctx);
+
+/* Number of members whose stop test has fired in the current sweep call
+ * (synchronizes). */
+pdr_status pdr_batch_stopped(pdr_batch *batch, int32_t *n_stopped);
+
+/* Autotuner: for every tiling bucket, time each supported arc tiling that
+ * covers the bucket's longest row (at most twice its size) with `reps`
+ * launches of the batched arc kernel on the current heights, and give the
+ * bucket's members the fastest. The run state is saved before and restored
+ * after (results are unchanged); buckets that end with the same tiling merge. */
+pdr_status pdr_batch_tune(pdr_batch *batch, int32_t reps);
+
+/* The current tiling buckets: *n_buckets receives their number, out[0 ..
+ * min(max_buckets, *n_buckets)) their descriptions. */
+pdr_status pdr_batch_buckets(pdr_batch *batch, int32_t max_buckets, pdr_bucket_info *out,
+                             int32_t *n_buckets);
+
+/* Measurement: `sweeps` batched passes without a stop test; kernel_ms[0] and
+ * kernel_ms[1] receive the summed device time of the height + objective
+ * launches and of all arc launches (HIP events on the batch stream;
+ * synchronizes). */
+pdr_status pdr_batch_profile_sweeps(pdr_batch *batch, int64_t sweeps, double *kernel_ms);
+
+/* Switch every member's storage precision (as pdr_set_precision). */
+pdr_status pdr_batch_set_precision(pdr_batch *batch, int32_t precision);
+
+/* Text of the last failure of the batch, or of the thread's last failed
+ * pdr_batch_init / pdr_init when batch is NULL. Never NULL. */
+const char *pdr_batch_last_error(const pdr_batch *batch);
+
+/* Release the batch, its members and all their device memory. */
+void pdr_batch_destroy(pdr_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,10 @@ STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVIC
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
            "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
            "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
-           "pdr_tiling", "pdr_destroy", "pdr_last_error"]
+           "pdr_tiling", "pdr_destroy", "pdr_last_error",
+           "pdr_batch_init", "pdr_batch_sweep", "pdr_batch_member", "pdr_batch_stopped",
+           "pdr_batch_tune", "pdr_batch_buckets", "pdr_batch_profile_sweeps",
+           "pdr_batch_set_precision", "pdr_batch_last_error", "pdr_batch_destroy"]
 
 
 class PdrError(RuntimeError):
@@ -57,7 +60,7 @@ class Options(C.Structure):
                 ("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32),
                 ("graph_sweeps", C.c_int32), ("height_chunk", C.c_int32),
                 ("cluster_size", C.c_int32), ("height_blocks", C.c_int32),
-                ("height_unroll", C.c_int32)]
+                ("height_unroll", C.c_int32), ("z_log_capacity", C.c_int32)]
 
 
 class Residual(C.Structure):
@@ -72,6 +75,19 @@ class Residual(C.Structure):
         d = {name: getattr(self, name) for name, _ in self._fields_}
         d["verdict"] = VERDICT[int(self.verdict)]
         return d
+
+
+class Instance(C.Structure):
+    """pdr_instance: one instance of Section 1 for pdr_batch_init."""
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("u", C.c_void_p), ("K", C.c_int32),
+                ("s", C.c_void_p), ("t", C.c_void_p), ("d", C.c_void_p)]
+
+
+class BucketInfo(C.Structure):
+    _fields_ = [("lanes_per_arc", C.c_int32), ("vec_per_lane", C.c_int32),
+                ("instances", C.c_int32), ("max_K", C.c_int32), ("arcs", C.c_int64),
+                ("ms", C.c_double)]
 
 
 _lib = None
@@ -106,8 +122,21 @@ def lib():
         L.pdr_destroy.restype = None
         L.pdr_last_error.argtypes = [P]
         L.pdr_last_error.restype = C.c_char_p
+        L.pdr_batch_init.argtypes = [C.POINTER(P), i32, C.POINTER(Instance), C.POINTER(Options)]
+        L.pdr_batch_sweep.argtypes = [P, i64, dbl, dbl]
+        L.pdr_batch_member.argtypes = [P, i32, C.POINTER(P)]
+        L.pdr_batch_stopped.argtypes = [P, C.POINTER(i32)]
+        L.pdr_batch_tune.argtypes = [P, i32]
+        L.pdr_batch_buckets.argtypes = [P, i32, C.POINTER(BucketInfo), C.POINTER(i32)]
+        L.pdr_batch_profile_sweeps.argtypes = [P, i64, P]
+        L.pdr_batch_set_precision.argtypes = [P, i32]
+        L.pdr_batch_last_error.argtypes = [P]
+        L.pdr_batch_last_error.restype = C.c_char_p
+        L.pdr_batch_destroy.argtypes = [P]
+        L.pdr_batch_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("pdr_default_options", "pdr_destroy", "pdr_last_error"):
+            if name not in ("pdr_default_options", "pdr_destroy", "pdr_last_error",
+                            "pdr_batch_last_error", "pdr_batch_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -279,6 +308,102 @@ class Context:
     def destroy(self):
         if self._h:
             lib().pdr_destroy(self._h)
+            self._h = C.c_void_p()
+
+    close = destroy
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many instances swept together (wraps pdr_batch_init ... pdr_batch_destroy).
+
+    ``member(i)`` returns instance i's context (owned by the batch) for
+    per-instance reads: flows, residual and verdict, z log."""
+
+    def __init__(self, instances, method=ESO, precision=FP64, stream=None, agd=None,
+                 graph_sweeps=0, z_log_capacity=0, lanes_per_arc=0, vec_per_lane=0):
+        L = lib()
+        self._h = C.c_void_p()
+        keep, arr = [], (Instance * len(instances))()
+        for q, inst in enumerate(instances):
+            a = [np.ascontiguousarray(inst.row_ptr, np.int64),
+                 np.ascontiguousarray(inst.col, np.int32), np.ascontiguousarray(inst.u, np.float64),
+                 np.ascontiguousarray(inst.s, np.int32), np.ascontiguousarray(inst.t, np.int32),
+                 np.ascontiguousarray(inst.d, np.float64)]
+            keep.append(a)
+            arr[q] = Instance(int(inst.n), int(a[1].shape[0]), _ptr(a[0]), _ptr(a[1]), _ptr(a[2]),
+                              int(a[3].shape[0]), _ptr(a[3]), _ptr(a[4]), _ptr(a[5]))
+        opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane, 1e-8, agd,
+                              graph_sweeps)
+        opt.z_log_capacity = int(z_log_capacity)
+        st = L.pdr_batch_init(C.byref(self._h), len(instances), arr, C.byref(opt))
+        if st != 0:
+            raise PdrError(st, L.pdr_batch_last_error(None).decode())
+        self.B = len(instances)
+        self.sizes = [(int(i.n), int(i.m), int(i.K)) for i in instances]
+        self._members = {}
+
+    def _check(self, st):
+        if st != 0:
+            raise PdrError(st, lib().pdr_batch_last_error(self._h).decode())
+
+    def sweep(self, max_sweeps: int, eps_obj: float = 0.0, z_target: float = 0.0):
+        self._check(lib().pdr_batch_sweep(self._h, int(max_sweeps), float(eps_obj),
+                                          float(z_target)))
+
+    def member(self, index: int) -> "Context":
+        if index not in self._members:
+            h = C.c_void_p()
+            self._check(lib().pdr_batch_member(self._h, int(index), C.byref(h)))
+            ctx = Context.__new__(Context)
+            ctx._h = h
+            ctx._keep = None
+            ctx.n, ctx.m, ctx.K = self.sizes[index]
+            self._members[index] = ctx
+        return self._members[index]
+
+    def stopped(self) -> int:
+        n = C.c_int32()
+        self._check(lib().pdr_batch_stopped(self._h, C.byref(n)))
+        return n.value
+
+    def tune(self, reps: int = 5):
+        self._check(lib().pdr_batch_tune(self._h, int(reps)))
+        return self.buckets()
+
+    def buckets(self):
+        n = C.c_int32()
+        self._check(lib().pdr_batch_buckets(self._h, 0, None, C.byref(n)))
+        arr = (BucketInfo * max(n.value, 1))()
+        self._check(lib().pdr_batch_buckets(self._h, n.value, arr, C.byref(n)))
+        return [{name: getattr(arr[q], name) for name, _ in BucketInfo._fields_}
+                for q in range(n.value)]
+
+    def profile_sweeps(self, sweeps: int) -> np.ndarray:
+        out = np.zeros(2, np.float64)
+        self._check(lib().pdr_batch_profile_sweeps(self._h, int(sweeps), _ptr(out)))
+        return out
+
+    def set_precision(self, precision: int):
+        self._check(lib().pdr_batch_set_precision(self._h, int(precision)))
+
+    def destroy(self):
+        if self._h:
+            for ctx in self._members.values():
+                ctx._h = C.c_void_p()
+            self._members = {}
+            lib().pdr_batch_destroy(self._h)
             self._h = C.c_void_p()
 
     close = destroy

@@ -69,6 +69,8 @@ struct pdr_ctx {
     double *Fsum = nullptr, *beta = nullptr, *zpart = nullptr, *maxpart = nullptr,
            *arcpart = nullptr, *resout = nullptr, *zlog = nullptr;
     int64_t nzpart = 0;
+    int64_t zlog_cap = pdr::kZLogCap;      // entries of the z log ring (power of two)
+    bool batch_member = false;             // owned by a pdr_batch
     Ctrl *ctrl = nullptr;
     // pinned host mirrors
     Ctrl *h_ctrl = nullptr;
@@ -348,7 +350,8 @@ hipError_t enqueue_passes(pdr_ctx *c, int64_t count, hipStream_t st)
     void *h = cur_h(c);
     const pdr::AgdParams prm = agd_params(c);
     for (int64_t q = 0; q < count; ++q) {
-        hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog, st);
+        hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog,
+                                          c->zlog_cap - 1, st);
         if (e == hipSuccess)
             e = c->method == PDR_ESO
                     ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, st)
@@ -400,6 +403,8 @@ void free_all(pdr_ctx *c)
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
+pdr_status set_precision_impl(pdr_ctx *c, int32_t precision);
+
 }  // namespace
 
 // ------------------------------------------------------------------ ABI
@@ -434,6 +439,7 @@ void pdr_default_options(pdr_options *opt)
     opt->cluster_size = 0;
     opt->height_blocks = 0;
     opt->height_unroll = 0;
+    opt->z_log_capacity = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -518,6 +524,9 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     if (opt.height_unroll != 0 && opt.height_unroll != 1 && opt.height_unroll != 2 &&
         opt.height_unroll != 4 && opt.height_unroll != 8)
         return invalid("height_unroll must be 0, 1, 2, 4 or 8");
+    if (opt.z_log_capacity < 0 || opt.z_log_capacity > pdr::kZLogCap ||
+        (opt.z_log_capacity & (opt.z_log_capacity - 1)) != 0)
+        return invalid("z_log_capacity must be 0 or a power of two up to 2^20");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
@@ -542,6 +551,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->cluster_size = opt.cluster_size == 0 ? kClusterAuto : opt.cluster_size;
     c->req_height_grid = opt.height_blocks;
     c->req_height_unroll = opt.height_unroll;
+    if (opt.z_log_capacity > 0) c->zlog_cap = opt.z_log_capacity;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
         if (st != PDR_OK) return init_fail(c, st, out);
@@ -567,7 +577,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
         const double w = c->precision == PDR_FP64 ? 8.0 : 4.0;
         const double mK = (double)m * c->Kp, nK = (double)n * c->Kp;
         double need = mK * w * (opt.method == PDR_GDM ? 2.0 : 1.0) + nK * w + nK * 8.0 * (c->precision == PDR_FP64 ? 0.0 : 1.0) +
-                      8.0 * (6.0 * m + 4.0 * n + 4.0 * K) + 8.0 * (double)pdr::kZLogCap +
+                      8.0 * (6.0 * m + 4.0 * n + 4.0 * K) + 8.0 * (double)(opt.z_log_capacity > 0 ? opt.z_log_capacity : pdr::kZLogCap) +
                       16.0 * (double)pdr::kHeightBlocksMax;
         size_t free_b = 0, total_b = 0;
         e = hipMemGetInfo(&free_b, &total_b);
@@ -673,7 +683,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     PDR_AL(c->maxpart, c->nzpart);
     PDR_AL(c->arcpart, 3 * (size_t)m);
     PDR_AL(c->resout, 8);
-    PDR_AL(c->zlog, pdr::kZLogCap);
+    PDR_AL(c->zlog, c->zlog_cap);
     PDR_AL(c->ctrl, 1);
 #undef PDR_AL
     e = hipHostMalloc((void **)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault);
@@ -814,6 +824,7 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
             err = hipEventRecord(ev[q][0], c->stream);
             if (err == hipSuccess)
                 err = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog,
+                                         c->zlog_cap - 1,
                                          c->stream);
             if (err == hipSuccess) err = hipEventRecord(ev[q][1], c->stream);
             if (err == hipSuccess)
@@ -969,12 +980,12 @@ pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
     st = sync_ctrl(c);
     if (st != PDR_OK) return st;
     const int64_t evals = c->h_ctrl->evals;
-    if (first + count > evals || first < evals - pdr::kZLogCap)
+    if (first + count > evals || first < evals - c->zlog_cap)
         return fail(c, PDR_ERR_INVALID, "z log range not available");
     int64_t done = 0;
     while (done < count) {
-        const int64_t pos = (first + done) & (pdr::kZLogCap - 1);
-        int64_t len = std::min<int64_t>(count - done, pdr::kZLogCap - pos);
+        const int64_t pos = (first + done) & (c->zlog_cap - 1);
+        int64_t len = std::min<int64_t>(count - done, c->zlog_cap - pos);
         PDR_CHECK(c, hipMemcpyAsync(host_out + done, c->zlog + pos, (size_t)len * 8,
                                     hipMemcpyDeviceToHost, c->stream));
         done += len;
@@ -987,6 +998,17 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
+    if (c->batch_member)
+        return fail(c, PDR_ERR_STATE, "a batch member switches precision with its batch");
+    return set_precision_impl(c, precision);
+}
+
+}  // extern "C"
+
+namespace {
+pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
+{
+    pdr_status st;
     if (precision != PDR_FP64 && precision != PDR_FP32_BULK)
         return fail(c, PDR_ERR_INVALID, "unknown precision");
     if (precision == c->precision) return PDR_OK;
@@ -1014,6 +1036,9 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
     PDR_CHECK(c, hipStreamSynchronize(c->stream));
     return PDR_OK;
 }
+}  // namespace
+
+extern "C" {
 
 pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, const double *v,
                          int64_t t, double z_prev)
@@ -1120,10 +1145,599 @@ pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
 
 void pdr_destroy(pdr_ctx *c)
 {
-    if (!c) return;
+    if (!c || c->batch_member) return;  // a batch frees its own members
     (void)hipSetDevice(c->device);
     free_all(c);
     delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+// A batch is a set of ordinary contexts (its members) on one stream and in one
+// storage precision, plus batched kernels that run a pass of every member at
+// once: one height launch whose blocks are apportioned to the members by work,
+// one objective launch with a block per member (each member keeps its own stop
+// test), and one arc launch per tiling bucket (members grouped by arc tiling,
+// largest first). Per-member reads (flows, residual, z log) go through the
+// member's own context.
+struct pdr_batch {
+    int32_t B = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t method = PDR_ESO;
+    int32_t precision = PDR_FP64;
+    int32_t graph_sweeps = 32;
+    int32_t height_unroll = 4;
+    std::vector<pdr_ctx *> members;
+    pdr::InstView *d_views = nullptr;
+    int2 *d_hmap = nullptr;
+    int64_t nhblocks = 0;
+    struct Bucket {
+        Tiling tl{1, 1};
+        std::vector<int32_t> members;  // largest m * Kp first
+        int2 *d_amap = nullptr;
+        int64_t nblocks = 0;
+        int32_t max_K = 0;
+        int64_t arcs = 0;
+        double ms = 0.0;  // arc-kernel time of the last tuning run
+    };
+    std::vector<Bucket> buckets;
+    int32_t *d_count = nullptr;
+    int32_t *h_count = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace {
+
+constexpr int64_t kBatchHeightBlocks = 2048;  // height blocks of a batched pass, about
+constexpr int32_t kBatchZLog = 4096;          // z log entries per member by default
+
+pdr_status bfail(pdr_batch *b, pdr_status st, const std::string &msg)
+{
+    b->err = msg;
+    return st;
+}
+
+pdr_status bdev_fail(pdr_batch *b, hipError_t e, const char *what)
+{
+    b->poisoned = true;
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    return PDR_ERR_DEVICE;
+}
+
+#define PDR_BCHECK(b, expr)                                           \
+    do {                                                              \
+        hipError_t _e = (expr);                                       \
+        if (_e != hipSuccess) return bdev_fail((b), _e, #expr);       \
+    } while (0)
+
+bool busable(pdr_batch *b, pdr_status *st)
+{
+    if (!b) {
+        *st = PDR_ERR_INVALID;
+        return false;
+    }
+    if (b->poisoned) {
+        *st = PDR_ERR_DEVICE;
+        return false;
+    }
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) {
+        *st = bdev_fail(b, e, "hipSetDevice");
+        return false;
+    }
+    return true;
+}
+
+// A member's failure belongs to the batch as well.
+pdr_status member_fail(pdr_batch *b, int32_t i, pdr_status st)
+{
+    if (st == PDR_ERR_DEVICE) b->poisoned = true;
+    b->err = "instance " + std::to_string(i) + ": " + b->members[i]->err;
+    return st;
+}
+
+template <typename T>
+hipError_t upload_vec(T **p, const std::vector<T> &v, hipStream_t st)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (v.empty() ? 1 : v.size()));
+    if (e == hipSuccess && !v.empty())
+        e = hipMemcpyAsync(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+void drop_graph(pdr_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+}
+
+// Block map of one bucket: every member's arcs in blocks of arcs_per_block(L).
+std::vector<int2> bucket_map(const pdr_batch *b, const std::vector<int32_t> &mem, int lanes)
+{
+    std::vector<int2> map;
+    const int64_t apb = pdr::arcs_per_block(lanes);
+    for (int32_t i : mem) {
+        const int64_t nb = (b->members[i]->m + apb - 1) / apb;
+        for (int64_t q = 0; q < nb; ++q) map.push_back(make_int2(i, (int)q));
+    }
+    return map;
+}
+
+// Rebuild the instance views, the height block map and the tiling buckets
+// from the members' current buffers and tilings.
+pdr_status build_maps(pdr_batch *b)
+{
+    drop_graph(b);
+    const int V = b->precision == PDR_FP64 ? 2 : 4;
+    const int32_t B = b->B;
+    std::vector<pdr::InstView> views(B);
+    std::vector<double> work(B);
+    double W = 0.0;
+    for (int32_t i = 0; i < B; ++i) {
+        pdr_ctx *c = b->members[i];
+        pdr::InstView &v = views[i];
+        v.g = c->g;
+        v.f = cur_f(c);
+        v.h = cur_h(c);
+        v.v = c->method == PDR_GDM ? cur_v(c) : nullptr;
+        v.Fsum = c->Fsum;
+        v.beta = c->beta;
+        v.prm = agd_params(c);
+        v.ctrl = c->ctrl;
+        v.zpart = c->zpart;
+        v.zlog = c->zlog;
+        v.zmask = c->zlog_cap - 1;
+        work[i] = (double)c->n * (double)(c->Kp / V);
+        W += work[i];
+    }
+    // members largest first: the big ones start first and the small ones fill in
+    std::vector<int32_t> order(B);
+    for (int32_t i = 0; i < B; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return (double)b->members[x]->m * b->members[x]->Kp >
+               (double)b->members[y]->m * b->members[y]->Kp;
+    });
+    std::vector<int2> hmap;
+    for (int32_t i : order) {
+        const int64_t need = std::max<int64_t>(1, (int64_t)std::ceil(work[i] / 256.0));
+        const int64_t share =
+            std::max<int64_t>(1, (int64_t)std::ceil(kBatchHeightBlocks * work[i] / std::max(W, 1.0)));
+        const int64_t nb = std::min<int64_t>({need, share, pdr::kHeightBlocksMax});
+        views[i].nzpart = (int32_t)nb;
+        for (int64_t q = 0; q < nb; ++q) hmap.push_back(make_int2(i, (int)q));
+    }
+    PDR_BCHECK(b, upload_vec(&b->d_views, views, b->stream));
+    PDR_BCHECK(b, upload_vec(&b->d_hmap, hmap, b->stream));
+    b->nhblocks = (int64_t)hmap.size();
+    // tiling buckets
+    for (auto &bk : b->buckets)
+        if (bk.d_amap) (void)hipFree(bk.d_amap);
+    b->buckets.clear();
+    for (int32_t i : order) {
+        const Tiling tl = b->members[i]->tiling;
+        auto it = std::find_if(b->buckets.begin(), b->buckets.end(), [&](const pdr_batch::Bucket &x) {
+            return x.tl.lanes == tl.lanes && x.tl.nv == tl.nv;
+        });
+        if (it == b->buckets.end()) {
+            b->buckets.emplace_back();
+            it = b->buckets.end() - 1;
+            it->tl = tl;
+        }
+        it->members.push_back(i);
+        it->max_K = std::max(it->max_K, b->members[i]->K);
+        it->arcs += b->members[i]->m;
+    }
+    for (auto &bk : b->buckets) {
+        const std::vector<int2> map = bucket_map(b, bk.members, bk.tl.lanes);
+        PDR_BCHECK(b, upload_vec(&bk.d_amap, map, b->stream));
+        bk.nblocks = (int64_t)map.size();
+    }
+    return PDR_OK;
+}
+
+hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st)
+{
+    const bool fp64 = b->precision == PDR_FP64;
+    for (int64_t q = 0; q < count; ++q) {
+        hipError_t e = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
+                                           b->height_unroll, st);
+        for (auto &bk : b->buckets)
+            if (e == hipSuccess)
+                e = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+pdr_status batch_graph(pdr_batch *b, hipGraphExec_t *out)
+{
+    if (!b->gexec) {
+        if (!b->cap_stream)
+            PDR_BCHECK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        PDR_BCHECK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_batch_passes(b, b->graph_sweeps, b->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+        PDR_BCHECK(b, e);
+        PDR_BCHECK(b, e2);
+        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PDR_BCHECK(b, e);
+    }
+    *out = b->gexec;
+    return PDR_OK;
+}
+
+pdr_status count_stopped(pdr_batch *b, int32_t *n)
+{
+    PDR_BCHECK(b, pdr::launch_bcount_stopped(b->d_views, b->B, b->d_count, b->stream));
+    PDR_BCHECK(b, hipMemcpyAsync(b->h_count, b->d_count, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 b->stream));
+    PDR_BCHECK(b, hipStreamSynchronize(b->stream));
+    *n = *b->h_count;
+    return PDR_OK;
+}
+
+void batch_free(pdr_batch *b)
+{
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (auto &bk : b->buckets)
+        if (bk.d_amap) (void)hipFree(bk.d_amap);
+    b->buckets.clear();
+    for (pdr_ctx *c : b->members) {
+        if (!c) continue;
+        c->batch_member = false;
+        pdr_destroy(c);
+    }
+    b->members.clear();
+    if (b->d_views) (void)hipFree(b->d_views);
+    if (b->d_hmap) (void)hipFree(b->d_hmap);
+    if (b->d_count) (void)hipFree(b->d_count);
+    if (b->h_count) (void)hipHostFree(b->h_count);
+    b->d_views = nullptr;
+    b->d_hmap = nullptr;
+    b->d_count = nullptr;
+    b->h_count = nullptr;
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    b->cap_stream = nullptr;
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+}
+
+// Per-member snapshot of the run state an arc kernel changes (and the control
+// record a height pass changes), for the tuner to put back.
+struct Snapshot {
+    std::vector<void *> bufs;
+    ~Snapshot()
+    {
+        for (void *p : bufs) (void)hipFree(p);
+    }
+};
+
+hipError_t snap_copy(Snapshot &sn, size_t slot, void *dst_or_src, size_t bytes, bool save,
+                     hipStream_t st)
+{
+    if (save) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e != hipSuccess) return e;
+        if (sn.bufs.size() <= slot) sn.bufs.resize(slot + 1, nullptr);
+        sn.bufs[slot] = p;
+        return hipMemcpyAsync(p, dst_or_src, bytes, hipMemcpyDeviceToDevice, st);
+    }
+    return hipMemcpyAsync(dst_or_src, sn.bufs[slot], bytes, hipMemcpyDeviceToDevice, st);
+}
+
+// Save (save = true) or restore the state of the listed members.
+hipError_t snapshot_members(pdr_batch *b, Snapshot &sn, const std::vector<int32_t> &mem, bool save)
+{
+    const size_t w = b->precision == PDR_FP64 ? 8 : 4;
+    size_t slot = 0;
+    for (int32_t i : mem) {
+        pdr_ctx *c = b->members[i];
+        const size_t mK = (size_t)c->m * c->Kp;
+        hipError_t e = snap_copy(sn, slot++, cur_f(c), mK * w, save, b->stream);
+        if (e == hipSuccess) e = snap_copy(sn, slot++, c->Fsum, (size_t)c->m * 8, save, b->stream);
+        if (e == hipSuccess) e = snap_copy(sn, slot++, c->beta, (size_t)c->m * 8, save, b->stream);
+        if (e == hipSuccess) e = snap_copy(sn, slot++, c->ctrl, sizeof(Ctrl), save, b->stream);
+        if (e == hipSuccess && c->method == PDR_GDM)
+            e = snap_copy(sn, slot++, cur_v(c), mK * w, save, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
+                          const pdr_options *opt_in)
+{
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PDR_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (B < 1 || !insts) {
+        g_init_error = "a batch needs B >= 1 instances";
+        return PDR_ERR_INVALID;
+    }
+    pdr_options opt;
+    pdr_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    auto *b = new pdr_batch();
+    b->B = B;
+    b->method = opt.method;
+    b->precision = opt.precision;
+    b->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
+    b->height_unroll = opt.height_unroll > 0 ? opt.height_unroll : kHeightUnrollAuto;
+    auto init_fail_b = [&](pdr_status st, const std::string &msg) {
+        g_init_error = msg;
+        batch_free(b);
+        delete b;
+        return st;
+    };
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return init_fail_b(PDR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (opt.stream) {
+        b->stream = (hipStream_t)opt.stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return init_fail_b(PDR_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        b->own_stream = true;
+    }
+    pdr_options mo = opt;
+    mo.stream = b->stream;
+    mo.graph_sweeps = -1;
+    if (mo.z_log_capacity == 0) mo.z_log_capacity = kBatchZLog;
+    b->members.assign(B, nullptr);
+    for (int32_t i = 0; i < B; ++i) {
+        const pdr_instance &in = insts[i];
+        pdr_status st = pdr_init(&b->members[i], in.n, in.m, in.row_ptr, in.col, in.u, in.K, in.s,
+                                 in.t, in.d, &mo);
+        if (st != PDR_OK)
+            return init_fail_b(st, "instance " + std::to_string(i) + ": " + g_init_error);
+        b->members[i]->batch_member = true;
+    }
+    e = hipMalloc((void **)&b->d_count, sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_count, sizeof(int32_t), hipHostMallocDefault);
+    if (e != hipSuccess)
+        return init_fail_b(e == hipErrorOutOfMemory ? PDR_ERR_OOM : PDR_ERR_DEVICE,
+                           std::string("batch buffers: ") + hipGetErrorString(e));
+    pdr_status st = build_maps(b);
+    if (st != PDR_OK) return init_fail_b(st, b->err);
+    *out = b;
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_member(pdr_batch *b, int32_t index, pdr_ctx **ctx)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (!ctx || index < 0 || index >= b->B) return bfail(b, PDR_ERR_INVALID, "no such member");
+    *ctx = b->members[index];
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_sweep(pdr_batch *b, int64_t max_sweeps, double eps_obj, double z_target)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (max_sweeps < 0) return bfail(b, PDR_ERR_INVALID, "max_sweeps must be >= 0");
+    if (std::isnan(eps_obj) || std::isnan(z_target))
+        return bfail(b, PDR_ERR_INVALID, "eps_obj and z_target must not be NaN");
+    PDR_BCHECK(b, pdr::launch_bbegin(b->d_views, b->B, eps_obj, z_target, b->stream));
+    const bool poll = eps_obj > 0.0 || z_target > 0.0;
+    const int64_t G = b->graph_sweeps;
+    hipGraphExec_t ge = nullptr;
+    if (G > 0 && max_sweeps >= G) {
+        st = batch_graph(b, &ge);
+        if (st != PDR_OK) return st;
+    }
+    int64_t s = 0, since = 0, every = 16;
+    while (s < max_sweeps) {
+        if (ge && max_sweeps - s >= G) {
+            PDR_BCHECK(b, hipGraphLaunch(ge, b->stream));
+            s += G;
+            since += G;
+        } else {
+            PDR_BCHECK(b, enqueue_batch_passes(b, 1, b->stream));
+            s += 1;
+            since += 1;
+        }
+        if (poll && since >= every && s < max_sweeps) {
+            since = 0;
+            if (every < 1024) every *= 2;
+            int32_t n = 0;
+            st = count_stopped(b, &n);
+            if (st != PDR_OK) return st;
+            if (n == b->B) break;
+        }
+    }
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_stopped(pdr_batch *b, int32_t *n_stopped)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (!n_stopped) return bfail(b, PDR_ERR_INVALID, "n_stopped is NULL");
+    return count_stopped(b, n_stopped);
+}
+
+pdr_status pdr_batch_buckets(pdr_batch *b, int32_t max_buckets, pdr_bucket_info *out,
+                             int32_t *n_buckets)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (!n_buckets || max_buckets < 0 || (max_buckets > 0 && !out))
+        return bfail(b, PDR_ERR_INVALID, "bad bucket output");
+    *n_buckets = (int32_t)b->buckets.size();
+    for (int32_t q = 0; q < max_buckets && q < (int32_t)b->buckets.size(); ++q) {
+        const auto &bk = b->buckets[q];
+        out[q].lanes_per_arc = bk.tl.lanes;
+        out[q].vec_per_lane = bk.tl.nv;
+        out[q].instances = (int32_t)bk.members.size();
+        out[q].max_K = bk.max_K;
+        out[q].arcs = bk.arcs;
+        out[q].ms = bk.ms;
+    }
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (reps < 1) return bfail(b, PDR_ERR_INVALID, "reps must be >= 1");
+    const bool fp64 = b->precision == PDR_FP64;
+    const int V = fp64 ? 2 : 4;
+    std::vector<int32_t> all(b->B);
+    for (int32_t i = 0; i < b->B; ++i) all[i] = i;
+    Snapshot sn;
+    PDR_BCHECK(b, snapshot_members(b, sn, all, true));
+    // heights of the current flows, so the arc kernels see the real workload
+    PDR_BCHECK(b, pdr::launch_bbegin(b->d_views, b->B, 0.0, 0.0, b->stream));
+    PDR_BCHECK(b, pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
+                                      b->height_unroll, b->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PDR_BCHECK(b, hipEventCreate(&e0));
+    PDR_BCHECK(b, hipEventCreate(&e1));
+    std::vector<Tiling> best(b->buckets.size());
+    std::vector<double> best_ms(b->buckets.size(), 0.0);
+    hipError_t err = hipSuccess;
+    for (size_t q = 0; q < b->buckets.size() && err == hipSuccess; ++q) {
+        const auto &bk = b->buckets[q];
+        int64_t maxvec = 1;
+        for (int32_t i : bk.members) maxvec = std::max<int64_t>(maxvec, b->members[i]->Kp / V);
+        const int64_t cap = 2 * (int64_t)pow2ceil(maxvec);
+        double bms = std::numeric_limits<double>::infinity();
+        Tiling bt = bk.tl;
+        int2 *amap = nullptr;
+        for (int L = 1; L <= kMaxLanes && err == hipSuccess; L *= 2)
+            for (int nv = 1; nv <= kMaxNv && err == hipSuccess; ++nv) {
+                if (!pdr::tiling_supported(L, nv) || (int64_t)L * nv < maxvec ||
+                    (int64_t)L * nv > cap)
+                    continue;
+                const Tiling tl{L, nv};
+                const std::vector<int2> map = bucket_map(b, bk.members, L);
+                err = upload_vec(&amap, map, b->stream);
+                if (err != hipSuccess) break;
+                // the same starting state for every candidate
+                err = snapshot_members(b, sn, all, false);
+                if (err == hipSuccess)
+                    err = pdr::launch_barc(b->method, b->d_views, amap, (int64_t)map.size(), fp64,
+                                           tl, b->stream);
+                if (err == hipSuccess) err = snapshot_members(b, sn, all, false);
+                if (err == hipSuccess) err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap,
+                                                                 b->nhblocks, fp64,
+                                                                 b->height_unroll, b->stream);
+                if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < reps && err == hipSuccess; ++r)
+                    err = pdr::launch_barc(b->method, b->d_views, amap, (int64_t)map.size(),
+                                           fp64, tl, b->stream);
+                if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err == hipSuccess && ms / reps < bms) {
+                    bms = ms / reps;
+                    bt = tl;
+                }
+            }
+        if (amap) (void)hipFree(amap);
+        best[q] = bt;
+        best_ms[q] = bms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err == hipSuccess) err = snapshot_members(b, sn, all, false);
+    PDR_BCHECK(b, err);
+    for (size_t q = 0; q < b->buckets.size(); ++q)
+        for (int32_t i : b->buckets[q].members) b->members[i]->tiling = best[q];
+    st = build_maps(b);
+    if (st != PDR_OK) return st;
+    // record the tuned time of each (possibly merged) bucket
+    for (auto &bk : b->buckets) {
+        bk.ms = 0.0;
+        for (size_t q = 0; q < best.size(); ++q)
+            if (best[q].lanes == bk.tl.lanes && best[q].nv == bk.tl.nv) bk.ms += best_ms[q];
+    }
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_profile_sweeps(pdr_batch *b, int64_t sweeps, double *kernel_ms)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (sweeps < 0 || !kernel_ms) return bfail(b, PDR_ERR_INVALID, "bad arguments");
+    const bool fp64 = b->precision == PDR_FP64;
+    hipEvent_t ev[3];
+    for (auto &x : ev) PDR_BCHECK(b, hipEventCreate(&x));
+    double tot[2] = {0.0, 0.0};
+    hipError_t err = pdr::launch_bbegin(b->d_views, b->B, 0.0, 0.0, b->stream);
+    for (int64_t s0 = 0; s0 < sweeps && err == hipSuccess; ++s0) {
+        err = hipEventRecord(ev[0], b->stream);
+        if (err == hipSuccess)
+            err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
+                                      b->height_unroll, b->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
+        for (auto &bk : b->buckets)
+            if (err == hipSuccess)
+                err = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl,
+                                       b->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+        for (int r = 0; r < 2 && err == hipSuccess; ++r) {
+            float ms = 0.0f;
+            err = hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+            tot[r] += ms;
+        }
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    PDR_BCHECK(b, err);
+    kernel_ms[0] = tot[0];
+    kernel_ms[1] = tot[1];
+    return PDR_OK;
+}
+
+pdr_status pdr_batch_set_precision(pdr_batch *b, int32_t precision)
+{
+    pdr_status st;
+    if (!busable(b, &st)) return st;
+    if (precision != PDR_FP64 && precision != PDR_FP32_BULK)
+        return bfail(b, PDR_ERR_INVALID, "unknown precision");
+    for (int32_t i = 0; i < b->B; ++i) {
+        st = set_precision_impl(b->members[i], precision);
+        if (st != PDR_OK) return member_fail(b, i, st);
+    }
+    b->precision = precision;
+    return build_maps(b);
+}
+
+const char *pdr_batch_last_error(const pdr_batch *b)
+{
+    if (!b) return g_init_error.c_str();
+    return b->err.c_str();
+}
+
+void pdr_batch_destroy(pdr_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    batch_free(b);
+    delete b;
 }
 
 }  // extern "C"

@@ -62,6 +62,21 @@ struct Tiling {
     int nv;
 };
 
+// One instance of a batch as the batched kernels see it (device-resident
+// array, one entry per instance). All instances of a batch share one storage
+// precision; f, h and v point into that instance's own buffers.
+struct InstView {
+    DevGraph g;
+    void *f, *h, *v;        // flows, heights, GDM velocities (v null unless GDM)
+    double *Fsum, *beta;
+    AgdParams prm;          // AGD/GDM parameters (beta_min depends on K)
+    Ctrl *ctrl;
+    double *zpart;          // 3 * nzpart objective partials
+    double *zlog;           // z log ring of zmask + 1 entries
+    int64_t zmask;
+    int32_t nzpart;         // height blocks of this instance in a batched pass
+};
+
 bool tiling_supported(int lanes, int nv);
 int64_t height_blocks(const DevGraph &g, int elem_bytes);
 
@@ -69,7 +84,8 @@ int64_t height_blocks(const DevGraph &g, int elem_bytes);
 hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t st);
 // Heights of the current flows, then the objective and stop test (two kernels).
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
-                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st);
+                         const double *Fsum, Ctrl *ctrl, double *zlog, int64_t zmask,
+                         hipStream_t st);
 hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, double *h64,
                                double *zpart, double *maxpart, hipStream_t st);
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
@@ -94,5 +110,19 @@ hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst
                         hipStream_t st);
 hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64,
                       hipStream_t st);
+
+// Batched passes over B instances (views: device array of B InstView).
+// hmap / amap: per logical block, (instance, block within that instance).
+hipError_t launch_bbegin(const InstView *views, int B, double eps_obj, double z_target,
+                         hipStream_t st);
+hipError_t launch_bheight(const InstView *views, int B, const int2 *hmap, int64_t nblocks,
+                          bool fp64, int unroll, hipStream_t st);
+// method: 0 ESO, 1 AGD, 2 GDM; blocks of `amap` hold ArcShape(tl.lanes) groups.
+hipError_t launch_barc(int method, const InstView *views, const int2 *amap, int64_t nblocks,
+                       bool fp64, Tiling tl, hipStream_t st);
+// Number of instances whose stop test has fired (written to device *out).
+hipError_t launch_bcount_stopped(const InstView *views, int B, int32_t *out, hipStream_t st);
+// Arcs handled by one block of an arc kernel with `lanes` lanes per arc.
+int arcs_per_block(int lanes);
 
 }  // namespace pdr

@@ -189,6 +189,18 @@ __global__ void k_begin(Ctrl *ctrl, double eps_obj, double z_target)
     }
 }
 
+__global__ void kb_begin(const InstView *__restrict__ views, int B, double eps_obj,
+                         double z_target)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) {
+        Ctrl *c = views[b].ctrl;
+        c->stopped = 0;
+        c->eps_obj = eps_obj;
+        c->z_target = z_target;
+    }
+}
+
 // ----------------------------------------------------------------- objective + stop test
 // One block: z = 1/2 sum of the height kernel's per-block partials of
 // Delta * h and of max(0, Fsum_e - u_e)^2 (Algorithm 1), the z log, the stop
@@ -198,9 +210,9 @@ __global__ void k_begin(Ctrl *ctrl, double eps_obj, double z_target)
 // z_noise = 1/2 sum_{i,k} (u32 a_ik)^2 / delta_i with a_ik the sum of the
 // magnitudes entering Delta_ik and u32 = 2^-24: the objective that rounding
 // each stored flow alone would leave; the FP32 run cannot get far below it.
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int nz,
-                                                 Ctrl *__restrict__ ctrl,
-                                                 double *__restrict__ zlog)
+__device__ __forceinline__ void reduce_core(const double *__restrict__ zpart, int nz,
+                                            Ctrl *__restrict__ ctrl, double *__restrict__ zlog,
+                                            int64_t zmask)
 {
     if (ctrl->stopped) return;
     __shared__ double sh[3][16];
@@ -230,7 +242,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpar
         const double zh = 0.5 * A, zp = 0.5 * B, z = zp + zh;
         ctrl->z_noise = 0.5 * Cn;
         const int64_t ev = ctrl->evals;
-        zlog[ev & (kZLogCap - 1)] = z;
+        zlog[ev & zmask] = z;
         ctrl->evals = ev + 1;
         ctrl->z = z;
         ctrl->z_psi = zp;
@@ -249,6 +261,20 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpar
     }
 }
 
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpart, int nz,
+                                                 Ctrl *__restrict__ ctrl,
+                                                 double *__restrict__ zlog, int64_t zmask)
+{
+    reduce_core(zpart, nz, ctrl, zlog, zmask);
+}
+
+// Batched: block b reduces instance b's partials into its own control record.
+__global__ __launch_bounds__(1024) void kb_reduce(const InstView *__restrict__ views)
+{
+    const InstView &I = views[blockIdx.x];
+    reduce_core(I.zpart, I.nzpart, I.ctrl, I.zlog, I.zmask);
+}
+
 // ----------------------------------------------------------------- excess -> height
 // Work item (i, q) computes Delta_ik = sum_in f - sum_out f + hatDelta_ik for the
 // V commodities of vector q of vertex i, then h = Delta / delta_i. Items are
@@ -258,15 +284,16 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ zpar
 // the arcs; zpart[b] and zpart[gridDim + b] receive the two partials.
 // RESID: write FP64 heights to h64 and the per-block max |Delta| (residual
 // report).
+// Work distribution: this block is block `blk` of `nblk` working on g; its
+// partials go to slot `part` (zpart[part], zpart[nblk + part], ...).
 template <typename T, bool RESID, int U>
-__global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
-                                                T *__restrict__ h, double *__restrict__ h64,
-                                                double *__restrict__ zpart,
-                                                double *__restrict__ maxpart,
-                                                const double *__restrict__ Fsum,
-                                                const Ctrl *__restrict__ ctrl)
+__device__ __forceinline__ void height_core(const DevGraph &g, const T *__restrict__ f,
+                                            T *__restrict__ h, double *__restrict__ h64,
+                                            double *__restrict__ zpart,
+                                            double *__restrict__ maxpart,
+                                            const double *__restrict__ Fsum, int64_t blk,
+                                            int64_t nblk, int64_t part)
 {
-    if (!RESID && ctrl->stopped) return;
     constexpr int V = VecT<T>::N;
     // FP32 storage: also accumulate the size of the rounding noise the stored
     // flows carry into each excess (see k_reduce)
@@ -284,9 +311,8 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
     const int CV = g.height_cv;
     const int64_t per_chunk = (int64_t)g.n * CV;
     const int64_t total = per_chunk * ((nvec + CV - 1) / CV);
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     double zs = 0.0, mx = 0.0;
-    for (int64_t gid = blk * 256 + threadIdx.x; gid < total; gid += (int64_t)gridDim.x * 256) {
+    for (int64_t gid = blk * 256 + threadIdx.x; gid < total; gid += nblk * 256) {
         const int64_t c = gid / per_chunk;
         const int64_t rem = gid - c * per_chunk;
         const int pos = (int)(rem / CV);
@@ -370,7 +396,7 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
     }
     double ps = 0.0;
     if constexpr (!RESID) {
-        for (int e = blockIdx.x * 256 + threadIdx.x; e < g.m; e += gridDim.x * 256) {
+        for (int64_t e = part * 256 + threadIdx.x; e < g.m; e += nblk * 256) {
             const double over = Fsum[e] - g.u[e];
             if (over > 0.0) ps += over * over;
         }
@@ -387,14 +413,41 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        zpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        zpart[part] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
         if (RESID) {
-            maxpart[blockIdx.x] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+            maxpart[part] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
         } else {
-            zpart[gridDim.x + blockIdx.x] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
-            zpart[2 * gridDim.x + blockIdx.x] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
+            zpart[nblk + part] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+            zpart[2 * nblk + part] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
         }
     }
+}
+
+template <typename T, bool RESID, int U>
+__global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
+                                                T *__restrict__ h, double *__restrict__ h64,
+                                                double *__restrict__ zpart,
+                                                double *__restrict__ maxpart,
+                                                const double *__restrict__ Fsum,
+                                                const Ctrl *__restrict__ ctrl)
+{
+    if (!RESID && ctrl->stopped) return;
+    height_core<T, RESID, U>(g, f, h, h64, zpart, maxpart, Fsum,
+                             xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
+}
+
+// Batched: hmap[logical block] = (instance, block within the instance); the
+// blocks of one instance are consecutive logical blocks, so an instance stays
+// on one XCD's range.
+template <typename T, int U>
+__global__ __launch_bounds__(256) void kb_height(const InstView *__restrict__ views,
+                                                 const int2 *__restrict__ hmap)
+{
+    const int2 it = hmap[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstView &I = views[it.x];
+    if (I.ctrl->stopped) return;
+    height_core<T, false, U>(I.g, (const T *)I.f, (T *)I.h, nullptr, I.zpart, nullptr, I.Fsum,
+                             it.y, I.nzpart, it.y);
 }
 
 // ----------------------------------------------------------------- arc kernels
@@ -415,21 +468,10 @@ struct ArcShape {
 // A <- {k in A: c_k > psi/2} until A is unchanged. Each pass is one group
 // reduction of (sum, count) over the register-resident c.
 template <typename T, int L, int NV>
-__global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restrict__ f,
-                                                          const T *__restrict__ h,
-                                                          double *__restrict__ Fsum,
-                                                          const Ctrl *__restrict__ ctrl)
+__device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, int64_t slot, int lane, double *lds)
 {
-    if (ctrl->stopped) return;
     constexpr int V = VecT<T>::N;
-    using S = ArcShape<L>;
-    __shared__ double lds[2 * kRedMax * S::NW];
     int phase = 0;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
-    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
-    const int64_t slot = blk * S::GPB + grp;
-    if (L <= 64 && slot >= g.m) return;
     const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
@@ -509,6 +551,40 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
     if (lane == 0) Fsum[e] = fs[0];
 }
 
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restrict__ f,
+                                                          const T *__restrict__ h,
+                                                          double *__restrict__ Fsum,
+                                                          const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    eso_arc<T, L, NV>(g, f, h, Fsum, slot, lane, lds);
+}
+
+// Batched: amap[logical block] = (instance, block within the instance's arcs).
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void kb_eso(const InstView *__restrict__ views,
+                                                          const int2 *__restrict__ amap)
+{
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int2 it = amap[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstView &I = views[it.x];
+    if (I.ctrl->stopped) return;
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = (int64_t)it.y * S::GPB + grp;
+    if (L <= 64 && slot >= I.g.m) return;
+    eso_arc<T, L, NV>(I.g, (T *)I.f, (const T *)I.h, I.Fsum, slot, lane, lds);
+}
+
 // PDR-AGD arc update (Algorithm 3): phi_k = h_ik - h_jk - psi,
 // df_k = max(-f_k, beta phi_k); the step is kept iff the exact change of the
 // edge subproblem objective (Expression 13, optimal slack),
@@ -516,23 +592,10 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
 // is <= 0; otherwise beta <- max(beta_min, alpha_dec beta). Every inc_period
 // iterations beta <- min(beta_max, alpha_inc beta).
 template <typename T, int L, int NV>
-__global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restrict__ f,
-                                                          const T *__restrict__ h,
-                                                          double *__restrict__ Fsum,
-                                                          double *__restrict__ beta,
-                                                          AgdParams prm,
-                                                          const Ctrl *__restrict__ ctrl)
+__device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, double *__restrict__ beta, const AgdParams &prm, const Ctrl *__restrict__ ctrl, int64_t slot, int lane, double *lds)
 {
-    if (ctrl->stopped) return;
     constexpr int V = VecT<T>::N;
-    using S = ArcShape<L>;
-    __shared__ double lds[2 * kRedMax * S::NW];
     int phase = 0;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
-    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
-    const int64_t slot = blk * S::GPB + grp;
-    if (L <= 64 && slot >= g.m) return;
     const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
@@ -599,13 +662,8 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     }
 }
 
-// PDR-GDM arc update (Algorithm 4): the step df and its accept test are those
-// of Algorithm 3 (k_agd); an accepted arc takes v' = gamma v + df and
-// f' = max(0, f + v'), a rejected one keeps f and v and lowers beta. beta's
-// periodic increase is as in k_agd.
 template <typename T, int L, int NV>
-__global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restrict__ f,
-                                                          T *__restrict__ vel,
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restrict__ f,
                                                           const T *__restrict__ h,
                                                           double *__restrict__ Fsum,
                                                           double *__restrict__ beta,
@@ -613,15 +671,42 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restri
                                                           const Ctrl *__restrict__ ctrl)
 {
     if (ctrl->stopped) return;
-    constexpr int V = VecT<T>::N;
     using S = ArcShape<L>;
     __shared__ double lds[2 * kRedMax * S::NW];
-    int phase = 0;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
+    agd_arc<T, L, NV>(g, f, h, Fsum, beta, prm, ctrl, slot, lane, lds);
+}
+
+// Batched: amap[logical block] = (instance, block within the instance's arcs).
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void kb_agd(const InstView *__restrict__ views,
+                                                          const int2 *__restrict__ amap)
+{
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int2 it = amap[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstView &I = views[it.x];
+    if (I.ctrl->stopped) return;
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = (int64_t)it.y * S::GPB + grp;
+    if (L <= 64 && slot >= I.g.m) return;
+    agd_arc<T, L, NV>(I.g, (T *)I.f, (const T *)I.h, I.Fsum, I.beta, I.prm, I.ctrl, slot, lane, lds);
+}
+
+// PDR-GDM arc update (Algorithm 4): the step df and its accept test are those
+// of Algorithm 3 (k_agd); an accepted arc takes v' = gamma v + df and
+// f' = max(0, f + v'), a rejected one keeps f and v and lowers beta. beta's
+// periodic increase is as in k_agd.
+template <typename T, int L, int NV>
+__device__ __forceinline__ void gdm_arc(const DevGraph &g, T *__restrict__ f, T *__restrict__ vel, const T *__restrict__ h, double *__restrict__ Fsum, double *__restrict__ beta, const AgdParams &prm, const Ctrl *__restrict__ ctrl, int64_t slot, int lane, double *lds)
+{
+    constexpr int V = VecT<T>::N;
+    int phase = 0;
     const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
@@ -692,6 +777,43 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restri
         beta[e] = nb;
         if (accept) Fsum[e] = red[2];
     }
+}
+
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restrict__ f,
+                                                          T *__restrict__ vel,
+                                                          const T *__restrict__ h,
+                                                          double *__restrict__ Fsum,
+                                                          double *__restrict__ beta,
+                                                          AgdParams prm,
+                                                          const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    gdm_arc<T, L, NV>(g, f, vel, h, Fsum, beta, prm, ctrl, slot, lane, lds);
+}
+
+// Batched: amap[logical block] = (instance, block within the instance's arcs).
+template <typename T, int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void kb_gdm(const InstView *__restrict__ views,
+                                                          const int2 *__restrict__ amap)
+{
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int2 it = amap[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstView &I = views[it.x];
+    if (I.ctrl->stopped) return;
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = (int64_t)it.y * S::GPB + grp;
+    if (L <= 64 && slot >= I.g.m) return;
+    gdm_arc<T, L, NV>(I.g, (T *)I.f, (T *)I.v, (const T *)I.h, I.Fsum, I.beta, I.prm, I.ctrl, slot, lane, lds);
 }
 
 // Fsum[e] = sum_k f[e, k] with the same lane layout and reduction tree as the
@@ -908,7 +1030,8 @@ hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t
 #define PDR_HEIGHT_UNROLL(X) X(1) X(2) X(4) X(8)
 
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
-                         const double *Fsum, Ctrl *ctrl, double *zlog, hipStream_t st)
+                         const double *Fsum, Ctrl *ctrl, double *zlog, int64_t zmask,
+                         hipStream_t st)
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     bool launched = false;
@@ -927,7 +1050,7 @@ hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, d
     if (!launched) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_reduce<<<1, 1024, 0, st>>>(zpart, (int)nb, ctrl, zlog);
+    k_reduce<<<1, 1024, 0, st>>>(zpart, (int)nb, ctrl, zlog, zmask);
     return hipGetLastError();
 }
 
@@ -1103,6 +1226,86 @@ hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64
     else
         k_pad<float><<<nb, 256, 0, st>>>(src, (float *)f, g.m, g.K, g.Kp);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- batched launchers
+int arcs_per_block(int lanes) { return lanes > 64 ? 1 : 256 / lanes; }
+
+hipError_t launch_bbegin(const InstView *views, int B, double eps_obj, double z_target,
+                         hipStream_t st)
+{
+    if (B <= 0) return hipSuccess;
+    kb_begin<<<(B + 255) / 256, 256, 0, st>>>(views, B, eps_obj, z_target);
+    return hipGetLastError();
+}
+
+// Number of instances whose stop test has fired, into *out (one block).
+__global__ __launch_bounds__(256) void kb_count_stopped(const InstView *__restrict__ views, int B,
+                                                        int32_t *__restrict__ out)
+{
+    __shared__ int part[4];
+    int cnt = 0;
+    for (int b = threadIdx.x; b < B; b += 256) cnt += views[b].ctrl->stopped ? 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_bcount_stopped(const InstView *views, int B, int32_t *out, hipStream_t st)
+{
+    kb_count_stopped<<<1, 256, 0, st>>>(views, B, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bheight(const InstView *views, int B, const int2 *hmap, int64_t nblocks,
+                          bool fp64, int unroll, hipStream_t st)
+{
+    if (B <= 0 || nblocks <= 0) return hipSuccess;
+    bool launched = false;
+#define PDR_BH(U_)                                                                             \
+    if (!launched && unroll == U_) {                                                           \
+        if (fp64)                                                                              \
+            kb_height<double, U_><<<(unsigned)nblocks, 256, 0, st>>>(views, hmap);             \
+        else                                                                                   \
+            kb_height<float, U_><<<(unsigned)nblocks, 256, 0, st>>>(views, hmap);              \
+        launched = true;                                                                       \
+    }
+    PDR_HEIGHT_UNROLL(PDR_BH)
+#undef PDR_BH
+    if (!launched) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    kb_reduce<<<B, 1024, 0, st>>>(views);
+    return hipGetLastError();
+}
+
+hipError_t launch_barc(int method, const InstView *views, const int2 *amap, int64_t nblocks,
+                       bool fp64, Tiling tl, hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)nblocks;
+#define PDR_BA(L_, NV_)                                                                        \
+    if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
+        constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
+        if (method == 0 && fp64)                                                               \
+            kb_eso<double, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                           \
+        else if (method == 0)                                                                  \
+            kb_eso<float, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                            \
+        else if (method == 1 && fp64)                                                          \
+            kb_agd<double, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                           \
+        else if (method == 1)                                                                  \
+            kb_agd<float, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                            \
+        else if (fp64)                                                                         \
+            kb_gdm<double, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                           \
+        else                                                                                   \
+            kb_gdm<float, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                            \
+        return hipGetLastError();                                                              \
+    }
+    PDR_TILINGS(PDR_BA)
+#undef PDR_BA
+    return hipErrorInvalidValue;
 }
 
 }  // namespace pdr
