@@ -104,6 +104,47 @@ def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=200):
                 precision_final="fp64" if n64 or precision == pdr.FP64 else "fp32")
 
 
+def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
+    """Batched sweeps of the uneven B-instance recipe: wall-clock updates/s of
+    plain sweeps (graph replays) before and after the tiling autotuner, and the
+    per-launch split from HIP events."""
+    from gen.batch import recipe_batch
+    t0 = time.perf_counter()
+    insts = recipe_batch(B, seed)
+    gen_s = time.perf_counter() - t0
+    w = 8 if precision == pdr.FP64 else 4
+    upd = sum(i.m * i.K for i in insts)
+    sweep_bytes = sum(w * (3 * i.m * i.K + 2 * i.n * i.K) for i in insts)
+    cert = {}
+    for i in insts:
+        cert[i.meta.get("certified", "unknown")] = cert.get(i.meta.get("certified", "unknown"), 0) + 1
+
+    def timed(b):
+        b.sweep(warmup)
+        pdr.device_synchronize()
+        t = time.perf_counter()
+        b.sweep(steps)
+        pdr.device_synchronize()
+        sec = time.perf_counter() - t
+        kms = b.profile_sweeps(steps)
+        return dict(ms_per_step=1e3 * sec / steps, updates_per_s=upd * steps / sec,
+                    frac=sweep_bytes / (sec / steps) / 1e9 / HBM_PEAK_GBS,
+                    kernel_ms_avg=dict(height_objective=kms[0] / steps, arc=kms[1] / steps))
+
+    t0 = time.perf_counter()
+    with pdr.Batch(insts, method=method, precision=precision) as b:
+        init_s = time.perf_counter() - t0
+        auto = timed(b)
+        auto["buckets"] = b.buckets()
+        tuned = b.tune(tune_reps)
+        after = timed(b)
+        after["buckets"] = tuned
+        after["height_blocks"] = b.height_blocks
+    return dict(workload=f"batch{B}_knn (seed {seed})", instances=B,
+                updates_per_sweep=upd, algorithmic_bytes_per_sweep=sweep_bytes,
+                certified=cert, generate_s=gen_s, init_s=init_s, auto=auto, tuned=after)
+
+
 def cpu_baseline(inst, sweeps):
     import oracle
     t0 = time.perf_counter()
@@ -126,6 +167,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=2 << 30,
                     help="buffer size of the plain-copy HBM reference (0: skip)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched 256-instance workload")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
     args = ap.parse_args()
@@ -201,6 +244,14 @@ def main():
             ttr[name] = r
         out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
                                        target=1e-8, **ttr)
+    if not args.no_batch:
+        bat = {}
+        for name, prec in (("eso_fp32", pdr.FP32_BULK), ("eso_fp64", pdr.FP64)):
+            r = time_batch(pdr, 256, 4, pdr.ESO, prec, 10, 3, 3)
+            print(f"[bench] batch {name}: auto {r['auto']['ms_per_step']:.3f} ms/sweep, tuned "
+                  f"{r['tuned']['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
+            bat[name] = r
+        out["batch"] = bat
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_sweeps} oracle sweeps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)

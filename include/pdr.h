@@ -264,7 +264,9 @@ typedef struct {
 /* Create a batch of B instances (deep copies; the caller keeps the arrays).
  * opt (NULL: defaults) applies to every member: method, precision, AGD/GDM
  * parameters, stream (NULL: the batch creates one; all members share it),
- * graph_sweeps (passes per captured batch graph). Members keep 4096 z log
+ * graph_sweeps (passes per captured batch graph), height_blocks (about this
+ * many blocks for the batched height launch, shared by work; 0 = 32768;
+ * more, smaller blocks balance uneven members better). Members keep 4096 z log
  * entries unless opt->z_log_capacity says otherwise. A failing instance fails
  * the whole call (status of that instance; pdr_batch_last_error(NULL) names it);
  * *out is NULL then. */
@@ -290,9 +292,11 @@ pdr_status pdr_batch_stopped(pdr_batch *batch, int32_t *n_stopped);
 /* Autotuner: for every tiling bucket, time each supported arc tiling that
  * covers the bucket's longest row (at most twice its size) with `reps`
  * launches of the batched arc kernel on the current heights, and give the
- * bucket's members the fastest. The run state is saved before and restored
+ * bucket's members the fastest; then time the batched height launch with
+ * 8192, 16384, 32768 and 65536 blocks and keep the fastest (written to
+ * *height_blocks unless NULL). The run state is saved before and restored
  * after (results are unchanged); buckets that end with the same tiling merge. */
-pdr_status pdr_batch_tune(pdr_batch *batch, int32_t reps);
+pdr_status pdr_batch_tune(pdr_batch *batch, int32_t reps, int64_t *height_blocks);
 
 /* The current tiling buckets: *n_buckets receives their number, out[0 ..
  * min(max_buckets, *n_buckets)) their descriptions. */

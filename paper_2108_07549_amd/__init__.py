@@ -126,7 +126,7 @@ def lib():
         L.pdr_batch_sweep.argtypes = [P, i64, dbl, dbl]
         L.pdr_batch_member.argtypes = [P, i32, C.POINTER(P)]
         L.pdr_batch_stopped.argtypes = [P, C.POINTER(i32)]
-        L.pdr_batch_tune.argtypes = [P, i32]
+        L.pdr_batch_tune.argtypes = [P, i32, C.POINTER(i64)]
         L.pdr_batch_buckets.argtypes = [P, i32, C.POINTER(BucketInfo), C.POINTER(i32)]
         L.pdr_batch_profile_sweeps.argtypes = [P, i64, P]
         L.pdr_batch_set_precision.argtypes = [P, i32]
@@ -332,7 +332,8 @@ class Batch:
     per-instance reads: flows, residual and verdict, z log."""
 
     def __init__(self, instances, method=ESO, precision=FP64, stream=None, agd=None,
-                 graph_sweeps=0, z_log_capacity=0, lanes_per_arc=0, vec_per_lane=0):
+                 graph_sweeps=0, z_log_capacity=0, lanes_per_arc=0, vec_per_lane=0,
+                 height_blocks=0):
         L = lib()
         self._h = C.c_void_p()
         keep, arr = [], (Instance * len(instances))()
@@ -347,6 +348,7 @@ class Batch:
         opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane, 1e-8, agd,
                               graph_sweeps)
         opt.z_log_capacity = int(z_log_capacity)
+        opt.height_blocks = int(height_blocks)
         st = L.pdr_batch_init(C.byref(self._h), len(instances), arr, C.byref(opt))
         if st != 0:
             raise PdrError(st, L.pdr_batch_last_error(None).decode())
@@ -379,7 +381,11 @@ class Batch:
         return n.value
 
     def tune(self, reps: int = 5):
-        self._check(lib().pdr_batch_tune(self._h, int(reps)))
+        """Autotune the arc tilings per bucket and the height launch; returns
+        the buckets (with their tuned arc-kernel ms)."""
+        hb = C.c_int64()
+        self._check(lib().pdr_batch_tune(self._h, int(reps), C.byref(hb)))
+        self.height_blocks = hb.value
         return self.buckets()
 
     def buckets(self):

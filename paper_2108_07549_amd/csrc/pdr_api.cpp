@@ -1170,6 +1170,7 @@ struct pdr_batch {
     int32_t precision = PDR_FP64;
     int32_t graph_sweeps = 32;
     int32_t height_unroll = 4;
+    int64_t height_budget = 0;  // height blocks of a batched pass, about
     std::vector<pdr_ctx *> members;
     pdr::InstView *d_views = nullptr;
     int2 *d_hmap = nullptr;
@@ -1186,6 +1187,12 @@ struct pdr_batch {
     std::vector<Bucket> buckets;
     int32_t *d_count = nullptr;
     int32_t *h_count = nullptr;
+    // arc launches of different buckets run on these streams side by side,
+    // forked from and joined back to the pass's stream with events
+    static constexpr int kBranches = 4;
+    hipStream_t aux[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
+    hipStream_t cap_aux[kBranches] = {};
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool poisoned = false;
@@ -1194,7 +1201,7 @@ struct pdr_batch {
 
 namespace {
 
-constexpr int64_t kBatchHeightBlocks = 2048;  // height blocks of a batched pass, about
+constexpr int64_t kBatchHeightBlocks = 32768;  // default height blocks of a batched pass
 constexpr int32_t kBatchZLog = 4096;          // z log entries per member by default
 
 pdr_status bfail(pdr_batch *b, pdr_status st, const std::string &msg)
@@ -1306,11 +1313,14 @@ pdr_status build_maps(pdr_batch *b)
         return (double)b->members[x]->m * b->members[x]->Kp >
                (double)b->members[y]->m * b->members[y]->Kp;
     });
+    // about height_budget blocks in all, each member its share by work (at
+    // least one block); every block grid-strides over its member's items
+    const double budget = (double)b->height_budget;
     std::vector<int2> hmap;
     for (int32_t i : order) {
         const int64_t need = std::max<int64_t>(1, (int64_t)std::ceil(work[i] / 256.0));
         const int64_t share =
-            std::max<int64_t>(1, (int64_t)std::ceil(kBatchHeightBlocks * work[i] / std::max(W, 1.0)));
+            std::max<int64_t>(1, (int64_t)std::ceil(budget * work[i] / std::max(W, 1.0)));
         const int64_t nb = std::min<int64_t>({need, share, pdr::kHeightBlocksMax});
         views[i].nzpart = (int32_t)nb;
         for (int64_t q = 0; q < nb; ++q) hmap.push_back(make_int2(i, (int)q));
@@ -1344,15 +1354,36 @@ pdr_status build_maps(pdr_batch *b)
     return PDR_OK;
 }
 
-hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st)
+// The bucket arc launches of one pass, forked over the branch streams `aux`
+// (largest bucket first, round robin) and joined back to st.
+hipError_t enqueue_batch_arcs(pdr_batch *b, hipStream_t st, hipStream_t *aux)
+{
+    const bool fp64 = b->precision == PDR_FP64;
+    const int nbr = (int)std::min<size_t>(pdr_batch::kBranches, b->buckets.size());
+    hipError_t e = hipSuccess;
+    if (nbr > 1) e = hipEventRecord(b->fork, st);
+    for (int r = 1; r < nbr && e == hipSuccess; ++r) e = hipStreamWaitEvent(aux[r], b->fork, 0);
+    for (size_t k = 0; k < b->buckets.size() && e == hipSuccess; ++k) {
+        const auto &bk = b->buckets[k];
+        hipStream_t s_k = nbr > 1 && k % nbr != 0 ? aux[k % nbr] : st;
+        e = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl, s_k);
+    }
+    for (int r = 1; r < nbr && e == hipSuccess; ++r) {
+        e = hipEventRecord(b->join[r], aux[r]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[r], 0);
+    }
+    return e;
+}
+
+// `count` batched passes on st: the height launch (objective and stop test
+// included), then the arc launches.
+hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st, hipStream_t *aux)
 {
     const bool fp64 = b->precision == PDR_FP64;
     for (int64_t q = 0; q < count; ++q) {
         hipError_t e = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
                                            b->height_unroll, st);
-        for (auto &bk : b->buckets)
-            if (e == hipSuccess)
-                e = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl, st);
+        if (e == hipSuccess) e = enqueue_batch_arcs(b, st, aux);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1363,8 +1394,10 @@ pdr_status batch_graph(pdr_batch *b, hipGraphExec_t *out)
     if (!b->gexec) {
         if (!b->cap_stream)
             PDR_BCHECK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        for (auto &x : b->cap_aux)
+            if (!x) PDR_BCHECK(b, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
         PDR_BCHECK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_batch_passes(b, b->graph_sweeps, b->cap_stream);
+        hipError_t e = enqueue_batch_passes(b, b->graph_sweeps, b->cap_stream, b->cap_aux);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
         PDR_BCHECK(b, e);
@@ -1408,6 +1441,14 @@ void batch_free(pdr_batch *b)
     b->d_hmap = nullptr;
     b->d_count = nullptr;
     b->h_count = nullptr;
+    for (auto &x : b->cap_aux)
+        if (x) (void)hipStreamDestroy(x);
+    for (auto &x : b->aux)
+        if (x) (void)hipStreamDestroy(x);
+    for (auto &x : b->join)
+        if (x) (void)hipEventDestroy(x);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    b->fork = nullptr;
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     b->cap_stream = nullptr;
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1482,6 +1523,7 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
     b->precision = opt.precision;
     b->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
     b->height_unroll = opt.height_unroll > 0 ? opt.height_unroll : kHeightUnrollAuto;
+    b->height_budget = opt.height_blocks > 0 ? opt.height_blocks : kBatchHeightBlocks;
     auto init_fail_b = [&](pdr_status st, const std::string &msg) {
         g_init_error = msg;
         batch_free(b);
@@ -1497,9 +1539,15 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
         if (e != hipSuccess) return init_fail_b(PDR_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
         b->own_stream = true;
     }
+    if (opt.height_blocks < 0 || opt.height_blocks > (1 << 20)) {
+        g_init_error = "height_blocks of a batch must be 0 or 1..2^20";
+        delete b;
+        return PDR_ERR_INVALID;
+    }
     pdr_options mo = opt;
     mo.stream = b->stream;
     mo.graph_sweeps = -1;
+    mo.height_blocks = 0;  // the batch budget is not a member setting
     if (mo.z_log_capacity == 0) mo.z_log_capacity = kBatchZLog;
     b->members.assign(B, nullptr);
     for (int32_t i = 0; i < B; ++i) {
@@ -1512,6 +1560,11 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
     }
     e = hipMalloc((void **)&b->d_count, sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_count, sizeof(int32_t), hipHostMallocDefault);
+    for (int r = 0; r < pdr_batch::kBranches && e == hipSuccess; ++r) {
+        e = hipStreamCreateWithFlags(&b->aux[r], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[r], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e != hipSuccess)
         return init_fail_b(e == hipErrorOutOfMemory ? PDR_ERR_OOM : PDR_ERR_DEVICE,
                            std::string("batch buffers: ") + hipGetErrorString(e));
@@ -1552,7 +1605,7 @@ pdr_status pdr_batch_sweep(pdr_batch *b, int64_t max_sweeps, double eps_obj, dou
             s += G;
             since += G;
         } else {
-            PDR_BCHECK(b, enqueue_batch_passes(b, 1, b->stream));
+            PDR_BCHECK(b, enqueue_batch_passes(b, 1, b->stream, b->aux));
             s += 1;
             since += 1;
         }
@@ -1596,7 +1649,7 @@ pdr_status pdr_batch_buckets(pdr_batch *b, int32_t max_buckets, pdr_bucket_info 
     return PDR_OK;
 }
 
-pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps)
+pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -1660,19 +1713,52 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps)
         best[q] = bt;
         best_ms[q] = bms;
     }
+    // each member's chosen tiling (the bucket list is rebuilt below)
+    std::vector<Tiling> member_tl(b->B);
+    for (size_t q = 0; q < b->buckets.size(); ++q)
+        for (int32_t i : b->buckets[q].members) member_tl[i] = best[q];
+    std::vector<std::pair<Tiling, double>> tuned_ms;
+    for (size_t q = 0; q < b->buckets.size(); ++q) tuned_ms.emplace_back(best[q], best_ms[q]);
+    // the height launch: blocks in all (each member's share by work)
+    int64_t best_budget = b->height_budget;
+    double best_hms = std::numeric_limits<double>::infinity();
+    for (int64_t cand = 8192; cand <= 65536 && err == hipSuccess; cand *= 2) {
+        b->height_budget = cand;
+        st = build_maps(b);
+        if (st != PDR_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
+                                  b->height_unroll, b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r)
+            err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
+                                      b->height_unroll, b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms / reps < best_hms) {
+            best_hms = ms / reps;
+            best_budget = cand;
+        }
+    }
+    b->height_budget = best_budget;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err == hipSuccess) err = snapshot_members(b, sn, all, false);
     PDR_BCHECK(b, err);
-    for (size_t q = 0; q < b->buckets.size(); ++q)
-        for (int32_t i : b->buckets[q].members) b->members[i]->tiling = best[q];
+    for (int32_t i = 0; i < b->B; ++i) b->members[i]->tiling = member_tl[i];
     st = build_maps(b);
     if (st != PDR_OK) return st;
+    if (height_blocks) *height_blocks = b->height_budget;
     // record the tuned time of each (possibly merged) bucket
     for (auto &bk : b->buckets) {
         bk.ms = 0.0;
-        for (size_t q = 0; q < best.size(); ++q)
-            if (best[q].lanes == bk.tl.lanes && best[q].nv == bk.tl.nv) bk.ms += best_ms[q];
+        for (const auto &x : tuned_ms)
+            if (x.first.lanes == bk.tl.lanes && x.first.nv == bk.tl.nv) bk.ms += x.second;
     }
     return PDR_OK;
 }
@@ -1693,10 +1779,7 @@ pdr_status pdr_batch_profile_sweeps(pdr_batch *b, int64_t sweeps, double *kernel
             err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
                                       b->height_unroll, b->stream);
         if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
-        for (auto &bk : b->buckets)
-            if (err == hipSuccess)
-                err = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl,
-                                       b->stream);
+        if (err == hipSuccess) err = enqueue_batch_arcs(b, b->stream, b->aux);
         if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
         if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
         for (int r = 0; r < 2 && err == hipSuccess; ++r) {
