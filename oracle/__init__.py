@@ -67,6 +67,8 @@ def lib():
         L.orc_run.argtypes = [i32, i32, P, P, P, i32, P, P, P, i32, C.POINTER(_AgdParams), i64,
                               dbl, dbl, P, P, P, P, P, P, P]
         L.orc_run.restype = i64
+        L.orc_eso_tangent.argtypes = [i32, i32, P, P, P, i32, P, P, P, P, P, i64, P, P, P, P]
+        L.orc_eso_tangent.restype = None
         L.orc_report.argtypes = [i32, i32, P, P, P, i32, P, P, P, P, dbl, P]
         L.orc_report.restype = i32
         _lib = L
@@ -245,6 +247,43 @@ def run(inst, method=ESO, T=1, eps_obj=0.0, z_target=0.0, params=None):
     st = State(inst, method, params)
     zs = st.run(T, eps_obj, z_target)
     return st, zs
+
+
+def eso_tangent(inst, T, du, dd, f0=None):
+    """T PDR-ESO sweeps from f0 (default 0) with the forward-mode tangent along
+    (du, dd): returns (f^T, fdot^T, z(f^T), dz along (du, dd))."""
+    m, K = inst.m, inst.K
+    f = np.zeros((m, K)) if f0 is None else np.array(f0, np.float64).reshape(m, K)
+    fdot = np.zeros((m, K))
+    z = np.zeros(1)
+    zd = np.zeros(1)
+    args = [_c(inst.row_ptr, np.int64), _c(inst.col, np.int32), _c(inst.u, np.float64),
+            _c(inst.s, np.int32), _c(inst.t, np.int32), _c(inst.d, np.float64),
+            _c(du, np.float64), _c(dd, np.float64)]
+    lib().orc_eso_tangent(inst.n, m, _p(args[0]), _p(args[1]), _p(args[2]), K, _p(args[3]),
+                          _p(args[4]), _p(args[5]), _p(args[6]), _p(args[7]), int(T), _p(f),
+                          _p(fdot), _p(z), _p(zd))
+    return f, fdot, float(z[0]), float(zd[0])
+
+
+def eso_gradient(inst, T, f0=None):
+    """Gradient of z(f^T) after T PDR-ESO sweeps with respect to every
+    capacity and demand, one forward-mode run per coordinate: (z, dz/du, dz/dd)."""
+    m, K = inst.m, inst.K
+    gu, gd = np.zeros(m), np.zeros(K)
+    z = None
+    for j in range(m + K):
+        du, dd = np.zeros(m), np.zeros(K)
+        if j < m:
+            du[j] = 1.0
+        else:
+            dd[j - m] = 1.0
+        _, _, z, zd = eso_tangent(inst, T, du, dd, f0)
+        if j < m:
+            gu[j] = zd
+        else:
+            gd[j - m] = zd
+    return z, gu, gd
 
 
 def report(inst, f, z_feasible_tol=1e-8) -> dict:

@@ -414,6 +414,105 @@ int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col
     return done;
 }
 
+/* Forward-mode derivative of T PDR-ESO sweeps (Algorithm 1 with Algorithm 2)
+ * along a direction (du, dd) of the capacities and demands, the starting flows
+ * f held fixed.
+ *
+ * The pass map is piecewise linear. The excess and heights are linear in (f, d),
+ * so their tangents are orc_excess applied to (fdot, dd). Per arc, Algorithm 2's
+ * result is f'_k = max(0, c_k - psi/2): when the arc is uncongested (psi = 0)
+ * the tangent is cdot_k where c_k > 0 and 0 elsewhere; when it is congested,
+ * psi = (sum_A c - u) / (1 + |A|/2) over the active set A = {k : f'_k > 0}, so
+ * psidot = (sum_A cdot - udot) / (1 + |A|/2) and f'dot_k = cdot_k - psidot/2 on A,
+ * 0 off it. On the measure-zero boundaries the branch Algorithm 2 takes is
+ * differentiated (a one-sided derivative).
+ *
+ * f: in the starting flows (m x K), out f^(T). fdot: out the tangent of f^(T).
+ * z_out / zdot_out: z(f^(T)) of Algorithm 1 and its directional derivative
+ * zdot = sum_e psi_e psidot_e + sum_{i,k} Delta_ik hdot_ik, with
+ * psidot_e = sum_k fdot_e,k - du_e when F_e > u_e, else 0. */
+void orc_eso_tangent(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col,
+                     const double *u, int32_t K, const int32_t *s, const int32_t *t_sink,
+                     const double *d, const double *du, const double *dd, int64_t T, double *f,
+                     double *fdot, double *z_out, double *zdot_out)
+{
+    const size_t mK = (size_t)m * K, nK = (size_t)n * K;
+    int32_t *tails = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *Delta = (double *)malloc(sizeof(double) * (nK ? nK : 1));
+    double *h = (double *)malloc(sizeof(double) * (nK ? nK : 1));
+    double *Ddot = (double *)malloc(sizeof(double) * (nK ? nK : 1));
+    double *hdot = (double *)malloc(sizeof(double) * (nK ? nK : 1));
+    double *fn = (double *)malloc(sizeof(double) * (mK ? mK : 1));
+    double *fdn = (double *)malloc(sizeof(double) * (mK ? mK : 1));
+    double *work = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+    double *cdot = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+    orc_tails(n, m, row_ptr, tails);
+    orc_degrees(n, m, row_ptr, col, deg);
+    memset(fdot, 0, sizeof(double) * mK);
+    for (int64_t pass = 0; pass < T; ++pass) {
+        orc_excess(n, m, row_ptr, col, K, s, t_sink, d, f, Delta, h);
+        orc_excess(n, m, row_ptr, col, K, s, t_sink, dd, fdot, Ddot, hdot);
+        for (int32_t e = 0; e < m; ++e) {
+            const double *hi = h + (size_t)tails[e] * K, *hj = h + (size_t)col[e] * K;
+            const double *hdi = hdot + (size_t)tails[e] * K, *hdj = hdot + (size_t)col[e] * K;
+            const double *fe = f + (size_t)e * K, *fde = fdot + (size_t)e * K;
+            double *fo = fn + (size_t)e * K, *fdo = fdn + (size_t)e * K;
+            double psi, r;
+            const int congested = orc_eso_edge(K, hi, hj, fe, u[e], fo, work, &psi, &r);
+            for (int32_t k = 0; k < K; ++k)
+                cdot[k] = 0.5 * ((hdi[k] + fde[k]) - (hdj[k] - fde[k]));
+            if (!congested) {
+                for (int32_t k = 0; k < K; ++k) fdo[k] = fo[k] > 0.0 ? cdot[k] : 0.0;
+            } else {
+                double sum_cdot = 0.0;
+                int32_t na = 0;
+                for (int32_t k = 0; k < K; ++k)
+                    if (fo[k] > 0.0) {
+                        sum_cdot += cdot[k];
+                        ++na;
+                    }
+                const double psidot = (sum_cdot - du[e]) / (1.0 + 0.5 * (double)na);
+                for (int32_t k = 0; k < K; ++k) fdo[k] = fo[k] > 0.0 ? cdot[k] - 0.5 * psidot : 0.0;
+            }
+        }
+        memcpy(f, fn, sizeof(double) * mK);
+        memcpy(fdot, fdn, sizeof(double) * mK);
+    }
+    /* the objective at f^(T) and its tangent */
+    orc_excess(n, m, row_ptr, col, K, s, t_sink, d, f, Delta, h);
+    orc_excess(n, m, row_ptr, col, K, s, t_sink, dd, fdot, Ddot, hdot);
+    double z_psi = 0.0, z_h = 0.0, zdot = 0.0;
+    for (int32_t e = 0; e < m; ++e) {
+        double F = 0.0, Fd = 0.0;
+        for (int32_t k = 0; k < K; ++k) {
+            F += f[(size_t)e * K + k];
+            Fd += fdot[(size_t)e * K + k];
+        }
+        if (F > u[e]) {
+            const double psi = F - u[e];
+            z_psi += 0.5 * psi * psi;
+            zdot += psi * (Fd - du[e]);
+        }
+    }
+    for (size_t q = 0; q < nK; ++q) {
+        z_h += 0.5 * Delta[q] * h[q];
+        zdot += Delta[q] * hdot[q];
+    }
+    *z_out = z_psi + z_h;
+    *zdot_out = zdot;
+    free(tails);
+    free(deg);
+    free(Delta);
+    free(h);
+    free(Ddot);
+    free(hdot);
+    free(fn);
+    free(fdn);
+    free(work);
+    free(cdot);
+}
+
 /*
  * Residual report for a pseudo-flow f (FP64):
  * out[0] z, out[1] z_psi, out[2] z_h, out[3] kkt_sq = sum rho^2 with

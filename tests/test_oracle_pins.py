@@ -17,7 +17,7 @@ import oracle
 from conftest import make_instance
 from exact_ref import (ExactInstance, edge_objective, exact_pdr, lp_feasible, qp_bruteforce,
                        qp_threshold)
-from gen.instance import recipe_small
+from gen.instance import recipe_grid4_k8, recipe_small
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -467,3 +467,81 @@ def test_thread_count_does_not_change_results(grid4):
         subprocess.check_call([sys.executable, "-c", code, path], env=env)
         outs.append(np.load(path))
     assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------ P13: forward-mode tangent
+def test_eso_tangent_two_vertex_closed_forms():
+    """d <= u: z_T = (d^2/2) 4^-T, so dz_T/dd = d 4^-T and dz_T/du = 0. d > u: the
+    limit f* = (d+u)/2 has z* = (d-u)^2/4, so dz*/dd = (d-u)/2 and dz*/du_01 = -(d-u)/2
+    (the reverse arc carries nothing)."""
+    inst = two_vertex(6.0, 8.0)
+    for T in (1, 2, 5, 9):
+        z, gu, gd = oracle.eso_gradient(inst, T)
+        assert z == pytest.approx(18.0 * 4.0 ** -T, rel=1e-14)
+        assert gd[0] == pytest.approx(6.0 * 4.0 ** -T, rel=1e-14)
+        assert np.all(gu == 0.0)
+    inst = two_vertex(10.0, 8.0)
+    z, gu, gd = oracle.eso_gradient(inst, 80)
+    assert z == pytest.approx(1.0, abs=1e-12)
+    assert gd[0] == pytest.approx(1.0, abs=1e-12)
+    assert gu[0] == pytest.approx(-1.0, abs=1e-12) and gu[1] == 0.0
+
+
+def _exact_z_after(ex, T):
+    """z(f^T) in exact rationals: the objective evaluated before pass T + 1."""
+    return exact_pdr(ex, "eso", T + 1)[1][T]
+
+
+def test_eso_tangent_matches_exact_difference_quotients():
+    """On a small congested instance the exact-rational difference quotient
+    (z(theta + eps e_j) - z(theta)) / eps with eps = 1e-30 equals the derivative
+    up to O(eps) away from kinks; the FP64 tangent must agree to 1e-9."""
+    inst = recipe_small("grid", 3, 3, seed=7, u_range=(2, 5), d_range=(4, 9))
+    T = 5
+    z, gu, gd = oracle.eso_gradient(inst, T)
+    ex = ExactInstance.from_instance(inst)
+    z0 = _exact_z_after(ex, T)
+    assert float(z0) == pytest.approx(z, rel=1e-12)
+    assert np.any(gu != 0.0), "the instance should have congested arcs"
+    eps = Fr(1, 10 ** 30)
+    rng = random.Random(3)
+    coords = rng.sample(range(inst.m), 6) + list(range(inst.m, inst.m + inst.K))
+    for j in coords:
+        u = list(ex.u)
+        d = list(ex.d)
+        if j < inst.m:
+            u[j] += eps
+        else:
+            d[j - inst.m] += eps
+        exj = ExactInstance(ex.n, inst.row_ptr, inst.col, u, inst.s, inst.t, d)
+        quot = float((_exact_z_after(exj, T) - z0) / eps)
+        tang = gu[j] if j < inst.m else gd[j - inst.m]
+        assert abs(quot - tang) <= 1e-9 * max(1.0, abs(tang)), (j, quot, tang)
+
+
+def test_eso_tangent_matches_central_differences():
+    """The grid4_k8 instance with demands x20 (infeasible, many congested arcs),
+    64 sweeps: forward-mode gradient vs central differences (h = 1e-6) of the
+    FP64 oracle's own z(f^T) for every capacity and demand."""
+    import dataclasses
+    base = recipe_grid4_k8()
+    inst = dataclasses.replace(base, d=base.d * 20.0)
+    T, h = 64, 1e-6
+    z, gu, gd = oracle.eso_gradient(inst, T)
+
+    def zT(i2):
+        return oracle.run(i2, oracle.ESO, T + 1)[1][T]
+
+    scale = max(np.abs(gu).max(), np.abs(gd).max())
+    for j in range(inst.m):
+        up, um = inst.u.copy(), inst.u.copy()
+        up[j] += h
+        um[j] -= h
+        fd = (zT(dataclasses.replace(inst, u=up)) - zT(dataclasses.replace(inst, u=um))) / (2 * h)
+        assert abs(fd - gu[j]) <= 1e-5 * scale, j
+    for k in range(inst.K):
+        dp, dm = inst.d.copy(), inst.d.copy()
+        dp[k] += h
+        dm[k] -= h
+        fd = (zT(dataclasses.replace(inst, d=dp)) - zT(dataclasses.replace(inst, d=dm))) / (2 * h)
+        assert abs(fd - gd[k]) <= 1e-5 * scale, k
