@@ -212,6 +212,24 @@ pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, cons
  * the stop test) and of the arc-update kernel. */
 pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
 
+/* Reverse-mode gradient (adjoint) of the objective after T PDR-ESO passes.
+ * Runs T passes from the current flows f^0 exactly as pdr_sweep(ctx, T, 0, 0)
+ * (Algorithm 1 with Algorithm 2; the context ends at f^T) and returns
+ * z(f^T) (Algorithm 1's objective) in *z_out and its gradient with respect to
+ * the capacities, grad_u[m] (caller's arc order), and the demands, grad_d[K],
+ * with f^0 held fixed. The pass map is piecewise linear (per arc: the
+ * identity on the active commodities of an uncongested arc; minus the mean
+ * over the active set A, weighted 1/(2 + |A|), on a congested one), so this is
+ * the exact derivative away from the measure-zero set where an active set or
+ * the congestion test changes (there: the one-sided derivative of the branch
+ * the forward pass takes). Flows are kept every `checkpoint` passes
+ * (0 = 16) and each segment is recomputed once during the reverse sweep;
+ * working memory ~ (T/checkpoint + checkpoint + 1) m K + n K doubles is
+ * allocated for the call. Needs method PDR_ESO and precision PDR_FP64
+ * (PDR_ERR_STATE otherwise). Synchronizes. */
+pdr_status pdr_adjoint(pdr_ctx *ctx, int64_t T, int32_t checkpoint, double *z_out,
+                       double *grad_u, double *grad_d);
+
 /* Measurement: the HBM bandwidth of a plain copy on the current device.
  * Copies `bytes` (rounded down to 16) between two freshly allocated device
  * buffers `iters` times with a 16-byte-vector tiled copy kernel (k_copy) and

@@ -445,14 +445,18 @@ void orc_eso_tangent(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t
     double *hdot = (double *)malloc(sizeof(double) * (nK ? nK : 1));
     double *fn = (double *)malloc(sizeof(double) * (mK ? mK : 1));
     double *fdn = (double *)malloc(sizeof(double) * (mK ? mK : 1));
-    double *work = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
-    double *cdot = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
     orc_tails(n, m, row_ptr, tails);
     orc_degrees(n, m, row_ptr, col, deg);
     memset(fdot, 0, sizeof(double) * mK);
     for (int64_t pass = 0; pass < T; ++pass) {
         orc_excess(n, m, row_ptr, col, K, s, t_sink, d, f, Delta, h);
         orc_excess(n, m, row_ptr, col, K, s, t_sink, dd, fdot, Ddot, hdot);
+        /* arcs are independent: threads split them, each with its own scratch */
+#pragma omp parallel if ((int64_t)m * K >= ORC_PAR_MIN)
+        {
+        double *work = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+        double *cdot = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+#pragma omp for schedule(static)
         for (int32_t e = 0; e < m; ++e) {
             const double *hi = h + (size_t)tails[e] * K, *hj = h + (size_t)col[e] * K;
             const double *hdi = hdot + (size_t)tails[e] * K, *hdj = hdot + (size_t)col[e] * K;
@@ -475,6 +479,9 @@ void orc_eso_tangent(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t
                 const double psidot = (sum_cdot - du[e]) / (1.0 + 0.5 * (double)na);
                 for (int32_t k = 0; k < K; ++k) fdo[k] = fo[k] > 0.0 ? cdot[k] - 0.5 * psidot : 0.0;
             }
+        }
+        free(work);
+        free(cdot);
         }
         memcpy(f, fn, sizeof(double) * mK);
         memcpy(fdot, fdn, sizeof(double) * mK);
@@ -509,8 +516,6 @@ void orc_eso_tangent(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t
     free(hdot);
     free(fn);
     free(fdn);
-    free(work);
-    free(cdot);
 }
 
 /*

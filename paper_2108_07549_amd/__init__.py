@@ -34,7 +34,7 @@ STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVIC
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
            "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
            "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
-           "pdr_tiling", "pdr_destroy", "pdr_last_error",
+           "pdr_tiling", "pdr_adjoint", "pdr_destroy", "pdr_last_error",
            "pdr_batch_init", "pdr_batch_sweep", "pdr_batch_member", "pdr_batch_stopped",
            "pdr_batch_tune", "pdr_batch_buckets", "pdr_batch_profile_sweeps",
            "pdr_batch_set_precision", "pdr_batch_last_error", "pdr_batch_destroy"]
@@ -117,6 +117,7 @@ def lib():
         L.pdr_set_state.argtypes = [P, P, P, P, i64, dbl]
         L.pdr_profile_sweeps.argtypes = [P, i64, P]
         L.pdr_measure_copy.argtypes = [i64, i32, P]
+        L.pdr_adjoint.argtypes = [P, i64, i32, P, P, P]
         L.pdr_tiling.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.pdr_destroy.argtypes = [P]
         L.pdr_destroy.restype = None
@@ -299,6 +300,16 @@ class Context:
         out = np.zeros(2, np.float64)
         self._check(lib().pdr_profile_sweeps(self._h, int(sweeps), _ptr(out)))
         return out
+
+    def adjoint(self, T: int, checkpoint: int = 0):
+        """T PDR-ESO passes (FP64) and the gradient of z(f^T) by reverse mode:
+        returns (z, dz/du, dz/dd)."""
+        z = np.zeros(1)
+        gu = np.zeros(max(self.m, 1))
+        gd = np.zeros(self.K)
+        self._check(lib().pdr_adjoint(self._h, int(T), int(checkpoint), _ptr(z), _ptr(gu),
+                                      _ptr(gd)))
+        return float(z[0]), gu[:self.m], gd
 
     def tiling(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

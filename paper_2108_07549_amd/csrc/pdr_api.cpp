@@ -1101,6 +1101,97 @@ pdr_status pdr_tiling(const pdr_ctx *c, int32_t *lanes_per_arc, int32_t *vec_per
     return PDR_OK;
 }
 
+pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
+                       double *grad_u, double *grad_d)
+{
+    pdr_status st;
+    if (!usable(c, &st)) return st;
+    if (T < 0 || checkpoint < 0 || !z_out || (c->m > 0 && !grad_u) || !grad_d)
+        return fail(c, PDR_ERR_INVALID, "need T >= 0, checkpoint >= 0 and output arrays");
+    if (c->method != PDR_ESO || c->precision != PDR_FP64)
+        return fail(c, PDR_ERR_STATE, "the adjoint needs a PDR_ESO context in PDR_FP64");
+    const int64_t C = checkpoint > 0 ? checkpoint : 16;
+    const int64_t nseg = (T + C - 1) / C;
+    const size_t mK = (size_t)c->m * c->Kp, nK = (size_t)c->n * c->Kp;
+    // working memory, released on every return
+    struct Bufs {
+        std::vector<void *> p;
+        ~Bufs()
+        {
+            for (void *q : p) (void)hipFree(q);
+        }
+        hipError_t get(double **out, size_t count)
+        {
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(double));
+            if (e == hipSuccess) p.push_back(q);
+            *out = (double *)q;
+            return e;
+        }
+    } bufs;
+    std::vector<double *> ckpt((size_t)nseg), seg((size_t)std::max<int64_t>(C - 1, 0));
+    double *gbar = nullptr, *cbar = nullptr, *Dbar = nullptr, *ubar = nullptr, *dbar = nullptr;
+    hipError_t e = hipSuccess;
+    for (auto &x : ckpt)
+        if (e == hipSuccess) e = bufs.get(&x, mK);
+    if (T > 1)
+        for (auto &x : seg)
+            if (e == hipSuccess) e = bufs.get(&x, mK);
+    if (e == hipSuccess) e = bufs.get(&gbar, mK);
+    if (e == hipSuccess) e = bufs.get(&cbar, mK);
+    if (e == hipSuccess) e = bufs.get(&Dbar, nK);
+    if (e == hipSuccess) e = bufs.get(&ubar, (size_t)c->m);
+    if (e == hipSuccess) e = bufs.get(&dbar, (size_t)c->K);
+    if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (adjoint)");
+    PDR_CHECK(c, e);
+    double *f = c->f64;
+    // ---- forward: T passes as pdr_sweep runs them, f kept every C passes
+    PDR_CHECK(c, pdr::launch_begin(c->ctrl, 0.0, 0.0, c->stream));
+    for (int64_t t = 0; t < T; ++t) {
+        if (t % C == 0)
+            PDR_CHECK(c, hipMemcpyAsync(ckpt[(size_t)(t / C)], f, mK * 8, hipMemcpyDeviceToDevice,
+                                        c->stream));
+        PDR_CHECK(c, enqueue_passes(c, 1, c->stream));
+    }
+    // ---- z(f^T) and the seed dz/df, dz/du, dz/dd at f^T (pdr_residual leaves
+    // the FP64 heights of f^T in h64)
+    pdr_residual_t res;
+    st = pdr_residual(c, &res);
+    if (st != PDR_OK && st != PDR_ERR_NUMERIC) return st;
+    PDR_CHECK(c, pdr::launch_adj_seed(c->g, c->Fsum, c->h64, gbar, ubar, dbar, c->stream));
+    // ---- reverse, segment by segment from the last
+    for (int64_t j = nseg - 1; j >= 0; --j) {
+        const int64_t a = j * C, b = std::min(T, a + C);
+        const double *prev = ckpt[(size_t)j];
+        for (int64_t k = 1; k < b - a; ++k) {  // f^(a+k) from f^(a+k-1)
+            double *nxt = seg[(size_t)(k - 1)];
+            PDR_CHECK(c, hipMemcpyAsync(nxt, prev, mK * 8, hipMemcpyDeviceToDevice, c->stream));
+            PDR_CHECK(c, pdr::launch_height_resid(c->g, true, prev, c->h64, c->zpart, c->maxpart,
+                                                  c->stream));
+            PDR_CHECK(c, pdr::launch_eso(c->g, true, c->tiling, nxt, c->h64, c->Fsum, c->ctrl,
+                                         c->stream));
+            prev = nxt;
+        }
+        for (int64_t t = b - 1; t >= a; --t) {
+            const double *ft = t == a ? ckpt[(size_t)j] : seg[(size_t)(t - a - 1)];
+            PDR_CHECK(c, pdr::launch_height_resid(c->g, true, ft, c->h64, c->zpart, c->maxpart,
+                                                  c->stream));
+            PDR_CHECK(c, pdr::launch_adj_pass(c->g, c->tiling, ft, c->h64, gbar, cbar, Dbar, ubar,
+                                              dbar, c->stream));
+        }
+    }
+    // the recomputation overwrote the row sums and heights: restore them for f^T
+    PDR_CHECK(c, pdr::launch_rowsum(c->g, true, c->tiling, f, c->Fsum, c->stream));
+    PDR_CHECK(c, pdr::launch_height_resid(c->g, true, f, c->h64, c->zpart, c->maxpart, c->stream));
+    if (c->m > 0)
+        PDR_CHECK(c, hipMemcpyAsync(grad_u, ubar, (size_t)c->m * 8, hipMemcpyDeviceToHost,
+                                    c->stream));
+    PDR_CHECK(c, hipMemcpyAsync(grad_d, dbar, (size_t)c->K * 8, hipMemcpyDeviceToHost, c->stream));
+    PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    *z_out = res.z;
+    return PDR_OK;
+}
+
 pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
 {
     if (bytes < 16 || iters < 1 || !gbps) {

@@ -1228,6 +1228,266 @@ hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- adjoint (FP64 ESO)
+// Reverse mode through PDR-ESO passes (Algorithm 1 with Algorithm 2). Per arc
+// the pass map is piecewise linear in c = f + (h_i - h_j)/2: with A the set
+// where f' = c - psi/2 > 0, an uncongested arc passes gbar through on A; a
+// congested one (psi = (sum_A c - u)/(1 + |A|/2)) gives
+// cbar_k = gbar_k - S/(2 + |A|) on A, S = sum_A gbar, and ubar += S/(2 + |A|).
+// Through h = Delta/delta and Delta_i = sum_in f - sum_out f + hatDelta_i:
+// Dbar_v = (sum_{e out of v} cbar_e - sum_{e into v} cbar_e) / (2 delta_v),
+// fbar_e = cbar_e + Dbar_head - Dbar_tail, dbar_k += Dbar_{s_k} - Dbar_{t_k}.
+
+// Seed of the reverse pass: gbar = dz/df = psi_e - (h_i - h_j) on real
+// commodities (0 on padding), ubar_e = dz/du_e = -psi_e. One item per
+// 16-byte vector of an arc row.
+__global__ __launch_bounds__(256) void k_adj_seed(DevGraph g, const double *__restrict__ Fsum,
+                                                  const double *__restrict__ h,
+                                                  double *__restrict__ gbar,
+                                                  double *__restrict__ ubar)
+{
+    const int nvec = g.Kp / 2;
+    const int64_t items = (int64_t)g.m * nvec;
+    for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+         it += (int64_t)gridDim.x * 256) {
+        const int64_t e = it / nvec;
+        const int q = (int)(it - e * nvec);
+        const double over = Fsum[e] - g.u[e];
+        const double psi = over > 0.0 ? over : 0.0;
+        const double *hi = h + (int64_t)g.tails[e] * g.Kp;
+        const double *hj = h + (int64_t)g.heads[e] * g.Kp;
+        double o[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int k = 2 * q + w;
+            o[w] = k < g.K ? psi - (hi[k] - hj[k]) : 0.0;
+        }
+        store_vec(gbar + e * g.Kp + 2 * q, o);
+        if (q == 0) ubar[e] = -psi;
+    }
+}
+
+// dbar_k = dz/dd_k through hatDelta: h_{s_k,k} - h_{t_k,k} (seed, accumulate 0)
+// or dbar_k += Dbar_{s_k,k} - Dbar_{t_k,k} (accumulate 1).
+__global__ __launch_bounds__(256) void k_adj_dbar(DevGraph g, const double *__restrict__ v,
+                                                  double *__restrict__ dbar, int accumulate)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= g.K) return;
+    const double x = v[(int64_t)g.s[k] * g.Kp + k] - v[(int64_t)g.t[k] * g.Kp + k];
+    dbar[k] = accumulate ? dbar[k] + x : x;
+}
+
+// ESO pass, reverse: from f^t, h^t and gbar = dz/df^(t+1), cbar (m x Kp) and
+// ubar += S/(2 + |A|). c and psi are recomputed with the forward kernel's
+// arithmetic and reduction tree (same tiling), so A is the forward pass's set.
+template <int L, int NV>
+__device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__restrict__ f,
+                                            const double *__restrict__ h,
+                                            const double *__restrict__ gbar,
+                                            double *__restrict__ cbar, double *__restrict__ ubar,
+                                            int64_t slot, int lane, double *lds)
+{
+    constexpr int V = 2;
+    int phase = 0;
+    const int64_t e = g.aorder[slot];
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    const double *fe = f + e * Kp;
+    const double *ge = gbar + e * Kp;
+    const double *hi = h + (int64_t)g.tails[e] * Kp;
+    const double *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+    double c[NV][V], gg[NV][V];
+    double red[2] = {0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            double a[V], b[V], x[V];
+            load_vec(fe + q * V, x);
+            load_vec(hi + q * V, a);
+            load_vec(hj + q * V, b);
+            load_vec(ge + q * V, gg[v]);
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const double cc = 0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
+                c[v][w] = cc;
+                if (cc > 0.0) {
+                    red[0] += cc;
+                    red[1] += 1.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < V; ++w) c[v][w] = gg[v][w] = 0.0;
+        }
+    }
+    group_sum<L, 2>(red, lds, phase);
+    double Ssum = red[0], P = red[1];
+    double psi = 0.0;
+    const bool congested = Ssum > u;
+    if (congested) {
+        double theta = 0.0;
+        for (;;) {
+            psi = (Ssum - u) / (1.0 + 0.5 * P);
+            const double th = fmax(theta, 0.5 * psi);
+            double r2[2] = {0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double cc = c[v][w];
+                    if (cc > th) {
+                        r2[0] += cc;
+                        r2[1] += 1.0;
+                    }
+                }
+            group_sum<L, 2>(r2, lds, phase);
+            if (r2[1] == P) break;
+            Ssum = r2[0];
+            P = r2[1];
+            theta = th;
+        }
+    }
+    const double half = 0.5 * psi;
+    double sa[2] = {0.0, 0.0};  // sum of gbar over A, |A|
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int w = 0; w < V; ++w)
+            if (c[v][w] - half > 0.0) {
+                sa[0] += gg[v][w];
+                sa[1] += 1.0;
+            }
+    if (congested) group_sum<L, 2>(sa, lds, phase);
+    const double share = congested ? sa[0] / (2.0 + sa[1]) : 0.0;
+    double *co = cbar + e * Kp;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        if (q < nvec) {
+            double o[V];
+#pragma unroll
+            for (int w = 0; w < V; ++w) o[w] = c[v][w] - half > 0.0 ? gg[v][w] - share : 0.0;
+            store_vec(co + q * V, o);
+        }
+    }
+    if (congested && lane == 0) ubar[e] += share;
+}
+
+template <int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_eso_bwd(DevGraph g,
+                                                              const double *__restrict__ f,
+                                                              const double *__restrict__ h,
+                                                              const double *__restrict__ gbar,
+                                                              double *__restrict__ cbar,
+                                                              double *__restrict__ ubar)
+{
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    eso_bwd_arc<L, NV>(g, f, h, gbar, cbar, ubar, slot, lane, lds);
+}
+
+// Dbar_v = (sum_out cbar - sum_in cbar) / (2 delta_v), one item per vector of
+// a vertex row (out-arcs in CSR order, then in-arcs).
+__global__ __launch_bounds__(256) void k_adj_vertex(DevGraph g, const double *__restrict__ cbar,
+                                                    double *__restrict__ Dbar)
+{
+    const int nvec = g.Kp / 2;
+    const int64_t items = (int64_t)g.n * nvec;
+    for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+         it += (int64_t)gridDim.x * 256) {
+        const int i = (int)(it / nvec);
+        const int q = (int)(it - (int64_t)i * nvec);
+        double acc[2] = {0.0, 0.0};
+        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+            double x[2];
+            load_vec(cbar + (int64_t)e * g.Kp + 2 * q, x);
+            acc[0] += x[0];
+            acc[1] += x[1];
+        }
+        for (int p = g.in_ptr[i]; p < g.in_ptr[i + 1]; ++p) {
+            double x[2];
+            load_vec(cbar + (int64_t)g.in_idx[p] * g.Kp + 2 * q, x);
+            acc[0] -= x[0];
+            acc[1] -= x[1];
+        }
+        const int dg = g.deg[i];
+        double o[2];
+        o[0] = dg > 0 ? acc[0] / (2.0 * dg) : 0.0;
+        o[1] = dg > 0 ? acc[1] / (2.0 * dg) : 0.0;
+        store_vec(Dbar + (int64_t)i * g.Kp + 2 * q, o);
+    }
+}
+
+// gbar_e = cbar_e + Dbar_head - Dbar_tail: dz/df^t from the pass's reverse.
+__global__ __launch_bounds__(256) void k_adj_arc(DevGraph g, const double *__restrict__ cbar,
+                                                 const double *__restrict__ Dbar,
+                                                 double *__restrict__ gbar)
+{
+    const int nvec = g.Kp / 2;
+    const int64_t items = (int64_t)g.m * nvec;
+    for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+         it += (int64_t)gridDim.x * 256) {
+        const int64_t e = it / nvec;
+        const int q = (int)(it - e * nvec);
+        double c[2], a[2], b[2], o[2];
+        load_vec(cbar + e * g.Kp + 2 * q, c);
+        load_vec(Dbar + (int64_t)g.heads[e] * g.Kp + 2 * q, a);
+        load_vec(Dbar + (int64_t)g.tails[e] * g.Kp + 2 * q, b);
+        o[0] = c[0] + a[0] - b[0];
+        o[1] = c[1] + a[1] - b[1];
+        store_vec(gbar + e * g.Kp + 2 * q, o);
+    }
+}
+
+hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *h, double *gbar,
+                           double *ubar, double *dbar, hipStream_t st)
+{
+    if (g.m > 0) {
+        k_adj_seed<<<grid_for((int64_t)g.m * (g.Kp / 2), 16384), 256, 0, st>>>(g, Fsum, h, gbar,
+                                                                              ubar);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_adj_dbar<<<(g.K + 255) / 256, 256, 0, st>>>(g, h, dbar, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const double *h,
+                           double *gbar, double *cbar, double *Dbar, double *ubar, double *dbar,
+                           hipStream_t st)
+{
+    if (g.m > 0) {
+        bool launched = false;
+#define PDR_AB(L_, NV_)                                                                        \
+    if (!launched && tl.lanes == L_ && tl.nv == NV_) {                                         \
+        constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
+        k_eso_bwd<L_, NV_><<<arc_blocks(g.m, L_), BS, 0, st>>>(g, f, h, gbar, cbar, ubar);     \
+        launched = true;                                                                       \
+    }
+        PDR_TILINGS(PDR_AB)
+#undef PDR_AB
+        if (!launched) return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_adj_vertex<<<grid_for((int64_t)g.n * (g.Kp / 2), 16384), 256, 0, st>>>(g, cbar, Dbar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_adj_dbar<<<(g.K + 255) / 256, 256, 0, st>>>(g, Dbar, dbar, 1);
+    e = hipGetLastError();
+    if (e != hipSuccess || g.m == 0) return e;
+    k_adj_arc<<<grid_for((int64_t)g.m * (g.Kp / 2), 16384), 256, 0, st>>>(g, cbar, Dbar, gbar);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- batched launchers
 int arcs_per_block(int lanes) { return lanes > 64 ? 1 : 256 / lanes; }
 
