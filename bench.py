@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -145,6 +147,21 @@ def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
                 certified=cert, generate_s=gen_s, init_s=init_s, auto=auto, tuned=after)
 
 
+def time_adjoint(pdr, inst, T, checkpoint, forward_ms):
+    """Wall time of pdr_adjoint (T forward passes, the recomputation and the
+    reverse sweep) from f = 0, and its cost in forward-sweep equivalents."""
+    with pdr.Context.from_instance(inst, method=pdr.ESO) as c:
+        c.adjoint(1, 1)  # warm up (kernels loaded, buffers touched)
+    with pdr.Context.from_instance(inst, method=pdr.ESO) as c:
+        pdr.device_synchronize()
+        t0 = time.perf_counter()
+        z, gu, gd = c.adjoint(T, checkpoint)
+        sec = time.perf_counter() - t0
+    return dict(T=T, checkpoint=checkpoint, seconds=sec, ms_per_pass=1e3 * sec / T,
+                forward_sweeps_per_pass=(1e3 * sec / T) / forward_ms, z=z,
+                max_abs_grad_u=float(np.max(np.abs(gu))), max_abs_grad_d=float(np.max(np.abs(gd))))
+
+
 def cpu_baseline(inst, sweeps):
     import oracle
     t0 = time.perf_counter()
@@ -169,6 +186,8 @@ def main():
                     help="buffer size of the plain-copy HBM reference (0: skip)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 256-instance workload")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint (reverse-mode gradient) timing")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
     args = ap.parse_args()
@@ -244,6 +263,11 @@ def main():
             ttr[name] = r
         out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
                                        target=1e-8, **ttr)
+    if not args.no_adjoint:
+        r = time_adjoint(pdr, inst, 8, 4, head["ms_per_step"])
+        print(f"[bench] adjoint T=8: {r['ms_per_pass']:.3f} ms per pass "
+              f"({r['forward_sweeps_per_pass']:.2f} forward sweeps)", file=sys.stderr, flush=True)
+        out["adjoint"] = r
     if not args.no_batch:
         bat = {}
         for name, prec in (("eso_fp32", pdr.FP32_BULK), ("eso_fp64", pdr.FP64)):
