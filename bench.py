@@ -114,6 +114,7 @@ def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
     t0 = time.perf_counter()
     insts = recipe_batch(B, seed)
     gen_s = time.perf_counter() - t0
+    print(f"[bench] batch: {B} instances generated ({gen_s:.1f} s)", file=sys.stderr, flush=True)
     w = 8 if precision == pdr.FP64 else 4
     upd = sum(i.m * i.K for i in insts)
     sweep_bytes = sum(w * (3 * i.m * i.K + 2 * i.n * i.K) for i in insts)
@@ -138,6 +139,8 @@ def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
         init_s = time.perf_counter() - t0
         auto = timed(b)
         auto["buckets"] = b.buckets()
+        print(f"[bench] batch: automatic tilings {auto['ms_per_step']:.3f} ms/sweep; tuning",
+              file=sys.stderr, flush=True)
         tuned = b.tune(tune_reps)
         after = timed(b)
         after["buckets"] = tuned

@@ -224,8 +224,8 @@ pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
  * the congestion test changes (there: the one-sided derivative of the branch
  * the forward pass takes). Flows are kept every `checkpoint` passes
  * (0 = 16) and each segment is recomputed once during the reverse sweep;
- * working memory ~ (T/checkpoint + checkpoint + 1) m K + n K doubles is
- * allocated for the call. Needs method PDR_ESO and precision PDR_FP64
+ * working memory of about (T/checkpoint + checkpoint) m K + (checkpoint + 1)
+ * n K doubles is allocated for the call. Needs method PDR_ESO and precision PDR_FP64
  * (PDR_ERR_STATE otherwise). Synchronizes. */
 pdr_status pdr_adjoint(pdr_ctx *ctx, int64_t T, int32_t checkpoint, double *z_out,
                        double *grad_u, double *grad_d);

@@ -11,7 +11,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpdr.so")
-SOURCES = [os.path.join(PKG, "csrc", "pdr_kernels.hip"), os.path.join(PKG, "csrc", "pdr_api.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", "pdr_kernels.hip"), os.path.join(PKG, "csrc", "pdr_api.cpp"),
+           os.path.join(PKG, "csrc", "pdr_batch.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -1,0 +1,87 @@
+// Host-side context of the library (private): the pdr_ctx record and the
+// helpers shared by the single-instance API (pdr_api.cpp) and batches
+// (pdr_batch.cpp). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pdr.h"
+#include "pdr_internal.h"
+
+namespace pdr_host {
+// Text of the calling thread's last failed init (pdr_last_error(NULL)).
+extern thread_local std::string g_init_error;
+constexpr int kMaxLanes = 1024;
+constexpr int kMaxNv = 20;
+// Vectors per commodity chunk in the height kernel: small enough that the
+// rows read by a window of neighbouring vertices stay in L2.
+constexpr int kHeightChunkAuto = 64;
+// Blocks of the grid-stride height kernel.
+constexpr int kHeightGridAuto = 2048;
+// Incident rows each height-kernel thread loads before summing them.
+constexpr int kHeightUnrollAuto = 4;
+// Vertices per locality cluster of the visiting order.
+constexpr int kClusterAuto = 64;
+// FP32 bulk hands over to the FP64 polish once z is within this factor of the
+// estimated FP32 floor z_noise / rate (see pdr_solve).
+constexpr double kFloorFactor = 5.0;
+}  // namespace pdr_host
+
+
+struct pdr_ctx {
+    int32_t n = 0, m = 0, K = 0, Kp = 0;
+    int32_t method = PDR_ESO;
+    int32_t precision = PDR_FP64;
+    pdr_agd_params agd{};
+    double beta_min = 0.0;
+    double z_feasible_tol = 1e-8;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t req_lanes = 0, req_nv = 0;
+    pdr::Tiling tiling{1, 1};
+    int32_t graph_sweeps = 32;             // passes per captured graph; 0 = no graphs
+    int32_t req_height_chunk = 0;          // 0 = automatic
+    int32_t cluster_size = 64;             // vertices per locality cluster; 1 = natural order
+    int32_t req_height_grid = 0;           // 0 = automatic
+    int32_t req_height_unroll = 0;         // 0 = automatic
+    hipStream_t cap_stream = nullptr;      // private stream used only for capture
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
+    bool poisoned = false;
+    std::string err;
+
+    pdr::DevGraph g{};
+    // instance arrays (device)
+    int32_t *d_row_ptr = nullptr, *d_tails = nullptr, *d_heads = nullptr, *d_in_ptr = nullptr,
+            *d_in_idx = nullptr, *d_deg = nullptr, *d_inj_ptr = nullptr, *d_inj_k = nullptr,
+            *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr;
+    double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
+    // run state (device)
+    double *f64 = nullptr, *h64 = nullptr, *v64 = nullptr;
+    float *f32 = nullptr, *h32 = nullptr, *v32 = nullptr;
+    double *Fsum = nullptr, *beta = nullptr, *zpart = nullptr, *maxpart = nullptr,
+           *arcpart = nullptr, *resout = nullptr, *zlog = nullptr;
+    int64_t nzpart = 0;
+    int64_t zlog_cap = pdr::kZLogCap;      // entries of the z log ring (power of two)
+    bool batch_member = false;             // owned by a pdr_batch
+    pdr::Ctrl *ctrl = nullptr;
+    // pinned host mirrors
+    pdr::Ctrl *h_ctrl = nullptr;
+    double *h_res = nullptr;
+    std::vector<void *> allocs;
+};
+
+
+namespace pdr_host {
+int pow2ceil(int64_t x);
+void *cur_f(pdr_ctx *c);  // flows, heights, velocities in the storage precision
+void *cur_h(pdr_ctx *c);
+void *cur_v(pdr_ctx *c);
+pdr::AgdParams agd_params(const pdr_ctx *c);
+// Switch a context's storage precision (pdr_set_precision without the check
+// that refuses batch members).
+pdr_status set_precision_impl(pdr_ctx *c, int32_t precision);
+}  // namespace pdr_host

@@ -111,17 +111,17 @@ hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst
 hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64,
                       hipStream_t st);
 
-// Reverse mode through FP64 PDR-ESO passes. Seed: gbar = dz/df at the final
-// flows (Fsum and h of those flows), ubar = dz/du, dbar = dz/dd (direct terms).
-hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *h, double *gbar,
+// Reverse mode through FP64 PDR-ESO passes. Seed at the final flows (Fsum and
+// h of those flows): cbar = dz/df (to be read with Dbar = 0), ubar = dz/du and
+// dbar = dz/dd (the direct terms).
+hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *h, double *cbar,
                            double *ubar, double *dbar, hipStream_t st);
-// One pass in reverse: f and h are the pass's input flows and heights; gbar
-// (dz/df of the pass's output) is replaced by dz/df of its input; ubar and
-// dbar accumulate. cbar (m x Kp) and Dbar (n x Kp) are scratch. tl is the
-// tiling the forward arc kernel used.
+// One pass in reverse: f and h are the pass's input flows and heights; on
+// entry dz/df of the pass's output is cbar + Dbar_head - Dbar_tail; on return
+// cbar and Dbar hold the pass's own, and ubar and dbar have accumulated. tl is
+// the tiling the forward arc kernel used.
 hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const double *h,
-                           double *gbar, double *cbar, double *Dbar, double *ubar, double *dbar,
-                           hipStream_t st);
+                           double *cbar, double *Dbar, double *ubar, double *dbar, hipStream_t st);
 
 // Batched passes over B instances (views: device array of B InstView).
 // hmap / amap: per logical block, (instance, block within that instance).

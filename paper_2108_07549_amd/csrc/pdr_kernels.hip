@@ -1238,9 +1238,10 @@ hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64
 // Dbar_v = (sum_{e out of v} cbar_e - sum_{e into v} cbar_e) / (2 delta_v),
 // fbar_e = cbar_e + Dbar_head - Dbar_tail, dbar_k += Dbar_{s_k} - Dbar_{t_k}.
 
-// Seed of the reverse pass: gbar = dz/df = psi_e - (h_i - h_j) on real
-// commodities (0 on padding), ubar_e = dz/du_e = -psi_e. One item per
-// 16-byte vector of an arc row.
+// Seed of the reverse sweep: dz/df = psi_e - (h_i - h_j) on real commodities
+// (0 on padding), written as cbar with Dbar = 0 (the form every reverse pass
+// reads), and ubar_e = dz/du_e = -psi_e. One item per 16-byte vector of an arc
+// row, arcs in the locality order.
 __global__ __launch_bounds__(256) void k_adj_seed(DevGraph g, const double *__restrict__ Fsum,
                                                   const double *__restrict__ h,
                                                   double *__restrict__ gbar,
@@ -1250,8 +1251,9 @@ __global__ __launch_bounds__(256) void k_adj_seed(DevGraph g, const double *__re
     const int64_t items = (int64_t)g.m * nvec;
     for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
          it += (int64_t)gridDim.x * 256) {
-        const int64_t e = it / nvec;
-        const int q = (int)(it - e * nvec);
+        const int64_t slot = it / nvec;  // arcs in the locality order
+        const int q = (int)(it - slot * nvec);
+        const int64_t e = g.aorder[slot];
         const double over = Fsum[e] - g.u[e];
         const double psi = over > 0.0 ? over : 0.0;
         const double *hi = h + (int64_t)g.tails[e] * g.Kp;
@@ -1278,15 +1280,18 @@ __global__ __launch_bounds__(256) void k_adj_dbar(DevGraph g, const double *__re
     dbar[k] = accumulate ? dbar[k] + x : x;
 }
 
-// ESO pass, reverse: from f^t, h^t and gbar = dz/df^(t+1), cbar (m x Kp) and
-// ubar += S/(2 + |A|). c and psi are recomputed with the forward kernel's
-// arithmetic and reduction tree (same tiling), so A is the forward pass's set.
+// ESO pass, reverse: from f^t, h^t and dz/df^(t+1) = cbar + Dbar_head -
+// Dbar_tail (the previous reverse pass's outputs, or the seed with Dbar = 0),
+// the pass's cbar (written over the arc's own cbar row: each lane rewrites
+// only the elements it read) and ubar += S/(2 + |A|). c and psi are recomputed
+// with the forward kernel's arithmetic and reduction tree (same tiling), so A
+// is the forward pass's set.
 template <int L, int NV>
 __device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__restrict__ f,
-                                            const double *__restrict__ h,
-                                            const double *__restrict__ gbar,
-                                            double *__restrict__ cbar, double *__restrict__ ubar,
-                                            int64_t slot, int lane, double *lds)
+                                            const double *__restrict__ h, double *cbar,
+                                            const double *__restrict__ Dbar,
+                                            double *__restrict__ ubar, int64_t slot, int lane,
+                                            double *lds)
 {
     constexpr int V = 2;
     int phase = 0;
@@ -1294,9 +1299,11 @@ __device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__r
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
     const double *fe = f + e * Kp;
-    const double *ge = gbar + e * Kp;
+    const double *ge = cbar + e * Kp;
     const double *hi = h + (int64_t)g.tails[e] * Kp;
     const double *hj = h + (int64_t)g.heads[e] * Kp;
+    const double *Dh = Dbar + (int64_t)g.heads[e] * Kp;
+    const double *Dt = Dbar + (int64_t)g.tails[e] * Kp;
     const double u = g.u[e];
     double c[NV][V], gg[NV][V];
     double red[2] = {0.0, 0.0};
@@ -1304,11 +1311,15 @@ __device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__r
     for (int v = 0; v < NV; ++v) {
         const int q = v * L + lane;
         if (q < nvec) {
-            double a[V], b[V], x[V];
+            double a[V], b[V], x[V], dh[V], dt[V];
             load_vec(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, b);
             load_vec(ge + q * V, gg[v]);
+            load_vec(Dh + q * V, dh);
+            load_vec(Dt + q * V, dt);
+#pragma unroll
+            for (int w = 0; w < V; ++w) gg[v][w] = gg[v][w] + dh[w] - dt[w];
 #pragma unroll
             for (int w = 0; w < V; ++w) {
                 const double cc = 0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
@@ -1380,8 +1391,8 @@ template <int L, int NV>
 __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso_bwd(DevGraph g,
                                                               const double *__restrict__ f,
                                                               const double *__restrict__ h,
-                                                              const double *__restrict__ gbar,
-                                                              double *__restrict__ cbar,
+                                                              double *cbar,
+                                                              const double *__restrict__ Dbar,
                                                               double *__restrict__ ubar)
 {
     using S = ArcShape<L>;
@@ -1391,11 +1402,12 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso_bwd(DevGraph g,
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    eso_bwd_arc<L, NV>(g, f, h, gbar, cbar, ubar, slot, lane, lds);
+    eso_bwd_arc<L, NV>(g, f, h, cbar, Dbar, ubar, slot, lane, lds);
 }
 
 // Dbar_v = (sum_out cbar - sum_in cbar) / (2 delta_v), one item per vector of
-// a vertex row (out-arcs in CSR order, then in-arcs).
+// a vertex row (out-arcs in CSR order, then in-arcs), vertices in the
+// locality order so the two reads of an arc's row fall close together.
 __global__ __launch_bounds__(256) void k_adj_vertex(DevGraph g, const double *__restrict__ cbar,
                                                     double *__restrict__ Dbar)
 {
@@ -1403,8 +1415,9 @@ __global__ __launch_bounds__(256) void k_adj_vertex(DevGraph g, const double *__
     const int64_t items = (int64_t)g.n * nvec;
     for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
          it += (int64_t)gridDim.x * 256) {
-        const int i = (int)(it / nvec);
-        const int q = (int)(it - (int64_t)i * nvec);
+        const int pos = (int)(it / nvec);  // vertices in the locality order
+        const int q = (int)(it - (int64_t)pos * nvec);
+        const int i = g.vorder[pos];
         double acc[2] = {0.0, 0.0};
         for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
             double x[2];
@@ -1426,27 +1439,6 @@ __global__ __launch_bounds__(256) void k_adj_vertex(DevGraph g, const double *__
     }
 }
 
-// gbar_e = cbar_e + Dbar_head - Dbar_tail: dz/df^t from the pass's reverse.
-__global__ __launch_bounds__(256) void k_adj_arc(DevGraph g, const double *__restrict__ cbar,
-                                                 const double *__restrict__ Dbar,
-                                                 double *__restrict__ gbar)
-{
-    const int nvec = g.Kp / 2;
-    const int64_t items = (int64_t)g.m * nvec;
-    for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
-         it += (int64_t)gridDim.x * 256) {
-        const int64_t e = it / nvec;
-        const int q = (int)(it - e * nvec);
-        double c[2], a[2], b[2], o[2];
-        load_vec(cbar + e * g.Kp + 2 * q, c);
-        load_vec(Dbar + (int64_t)g.heads[e] * g.Kp + 2 * q, a);
-        load_vec(Dbar + (int64_t)g.tails[e] * g.Kp + 2 * q, b);
-        o[0] = c[0] + a[0] - b[0];
-        o[1] = c[1] + a[1] - b[1];
-        store_vec(gbar + e * g.Kp + 2 * q, o);
-    }
-}
-
 hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *h, double *gbar,
                            double *ubar, double *dbar, hipStream_t st)
 {
@@ -1461,15 +1453,14 @@ hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *
 }
 
 hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const double *h,
-                           double *gbar, double *cbar, double *Dbar, double *ubar, double *dbar,
-                           hipStream_t st)
+                           double *cbar, double *Dbar, double *ubar, double *dbar, hipStream_t st)
 {
     if (g.m > 0) {
         bool launched = false;
 #define PDR_AB(L_, NV_)                                                                        \
     if (!launched && tl.lanes == L_ && tl.nv == NV_) {                                         \
         constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
-        k_eso_bwd<L_, NV_><<<arc_blocks(g.m, L_), BS, 0, st>>>(g, f, h, gbar, cbar, ubar);     \
+        k_eso_bwd<L_, NV_><<<arc_blocks(g.m, L_), BS, 0, st>>>(g, f, h, cbar, Dbar, ubar);     \
         launched = true;                                                                       \
     }
         PDR_TILINGS(PDR_AB)
@@ -1482,9 +1473,6 @@ hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_adj_dbar<<<(g.K + 255) / 256, 256, 0, st>>>(g, Dbar, dbar, 1);
-    e = hipGetLastError();
-    if (e != hipSuccess || g.m == 0) return e;
-    k_adj_arc<<<grid_for((int64_t)g.m * (g.Kp / 2), 16384), 256, 0, st>>>(g, cbar, Dbar, gbar);
     return hipGetLastError();
 }
 

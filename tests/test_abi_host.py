@@ -117,3 +117,26 @@ def test_null_context_calls_are_invalid():
     assert L.pdr_flows(None, None) == 1
     assert L.pdr_residual(None, None) == 1
     L.pdr_destroy(None)  # ignored
+
+
+def test_batch_init_rejects_empty_input():
+    """Checked before any device call."""
+    import ctypes as C
+    L = pdr.lib()
+    h = C.c_void_p()
+    arr = (pdr.Instance * 1)()
+    assert L.pdr_batch_init(C.byref(h), 0, arr, None) == 1
+    assert "B >= 1" in L.pdr_batch_last_error(None).decode()
+    assert L.pdr_batch_init(C.byref(h), 2, None, None) == 1
+    assert not h.value
+
+
+def test_batch_and_adjoint_null_handles_are_invalid():
+    import ctypes as C
+    L = pdr.lib()
+    assert L.pdr_batch_sweep(None, 1, 0.0, 0.0) == 1
+    assert L.pdr_batch_tune(None, 1, None) == 1
+    assert L.pdr_batch_stopped(None, None) == 1
+    z = C.c_double()
+    assert L.pdr_adjoint(None, 1, 0, C.byref(z), None, None) == 1
+    L.pdr_batch_destroy(None)  # ignored

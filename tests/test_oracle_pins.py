@@ -545,3 +545,24 @@ def test_eso_tangent_matches_central_differences():
         dm[k] -= h
         fd = (zT(dataclasses.replace(inst, d=dp)) - zT(dataclasses.replace(inst, d=dm))) / (2 * h)
         assert abs(fd - gd[k]) <= 1e-5 * scale, k
+
+
+def test_violation_bounds_follow_from_z():
+    """P9: z >= psi_e^2 / 2 and z >= Delta_ik^2 / (2 delta_i) term by term, so at
+    every iterate max psi <= sqrt(2 z) and |Delta_ik| <= sqrt(2 z delta_i); the
+    report's max congestion and max |excess| are the maxima of those terms."""
+    inst = recipe_small("knn", 30, 12, seed=9, u_range=(1, 4), d_range=(2, 8))
+    deg = oracle.degrees(inst)
+    st = oracle.State(inst, oracle.ESO)
+    done = 0
+    for T in (0, 1, 5, 40):
+        st.run(T - done)
+        done = T
+        rep = oracle.report(inst, st.f)
+        Delta, _ = oracle.excess(inst, st.f)
+        _, psi = oracle.congestion(inst, st.f)
+        z = rep["z"]
+        assert rep["max_congestion"] == pytest.approx(float(psi.max()), rel=1e-14, abs=0)
+        assert rep["max_abs_excess"] == pytest.approx(float(np.abs(Delta).max()), rel=1e-14, abs=0)
+        assert psi.max() <= math.sqrt(2 * z) * (1 + 1e-12)
+        assert np.all(np.abs(Delta) <= np.sqrt(2 * z * deg)[:, None] * (1 + 1e-12))
