@@ -3,8 +3,9 @@
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package. It never serves the product path and shares no code with it.
 
-``pdr_oracle.c`` holds the arithmetic (Algorithms 1-3 and the definitions of
-Sections 3-5 in FP64); this module builds it with gcc and wraps it with ctypes.
+``pdr_oracle.c`` holds the arithmetic (Algorithms 1-4, the capacity-enforcing
+edge step for Section 6's formulation and the definitions of Sections 3-5, in
+FP64); this module builds it with gcc and wraps it with ctypes.
 Flows are m x K arrays in the caller's CSR arc order.
 """
 from __future__ import annotations
@@ -21,7 +22,7 @@ _SRC = os.path.join(_HERE, "pdr_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-ESO, AGD, GDM = 0, 1, 2
+ESO, AGD, GDM, CAP = 0, 1, 2, 3
 VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
 
 
@@ -58,6 +59,8 @@ def lib():
         L.orc_objective_edge_form.restype = dbl
         L.orc_eso_edge.argtypes = [i32, P, P, P, dbl, P, P, P, P]
         L.orc_eso_edge.restype = C.c_int
+        L.orc_cap_edge.argtypes = [i32, P, P, P, dbl, P, P, P]
+        L.orc_cap_edge.restype = C.c_int
         L.orc_agd_edge.argtypes = [i32, P, P, P, dbl, dbl, dbl, i64, P, dbl, dbl, dbl, dbl, i32,
                                    P, P]
         L.orc_agd_edge.restype = C.c_int
@@ -144,6 +147,18 @@ def eso_edge(hi, hj, fe, u):
     r = np.zeros(1)
     cg = lib().orc_eso_edge(K, _p(hi), _p(hj), _p(fe), float(u), _p(out), _p(work), _p(psi), _p(r))
     return out, float(psi[0]), float(r[0]), bool(cg)
+
+
+def cap_edge(hi, hj, fe, u):
+    """Capacity-enforcing edge step (Section 6's formulation): returns
+    (f_new, lambda, binds)."""
+    hi, hj, fe = (_c(x, np.float64) for x in (hi, hj, fe))
+    K = hi.shape[0]
+    out = np.zeros(K)
+    work = np.zeros(max(K, 1))
+    lam = np.zeros(1)
+    b = lib().orc_cap_edge(K, _p(hi), _p(hj), _p(fe), float(u), _p(out), _p(work), _p(lam))
+    return out, float(lam[0]), bool(b)
 
 
 def gdm_edge(hi, hj, fe, ve, u, t, beta, params=None):

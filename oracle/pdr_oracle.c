@@ -43,6 +43,7 @@
 #define ORC_ESO 0
 #define ORC_AGD 1
 #define ORC_GDM 2
+#define ORC_CAP 3
 /* parallel regions are used only when a loop has this much work */
 #define ORC_PAR_MIN 65536
 
@@ -226,6 +227,58 @@ int orc_eso_edge(int32_t K, const double *hi, const double *hj, const double *fe
     return congested;
 }
 
+/* Capacity-enforcing edge step (the formulation of Section 6: conservation
+ * relaxed, capacity kept). The arc's part of the edge-form objective of
+ * Expression 8 without the congestion term, 1/2 sum_k [(h_ik - x_k)^2 +
+ * (h_jk + x_k)^2] over the step x = f' - f, is minimised subject to
+ * sum_k f'_k <= u and f' >= 0: up to a constant this is the Euclidean
+ * projection of c_k = ((h_ik + f_k) - (h_jk - f_k)) / 2 onto the capped
+ * simplex. Its KKT conditions give f'_k = max(0, c_k - lambda) with lambda >= 0
+ * and lambda (sum f' - u) = 0: lambda = 0 when sum max(0, c) <= u; otherwise,
+ * with the positive c sorted descending and prefix sums S_p, lambda =
+ * (S_p - u) / p for the first p with c_(p+1) <= lambda <= c_(p)
+ * (c_(M+1) := 0; lambda = c_(p) happens at u = 0).
+ * Writes the new flows and *lambda_out; returns 1 when the capacity binds. */
+int orc_cap_edge(int32_t K, const double *hi, const double *hj, const double *fe, double u,
+                 double *fout, double *work, double *lambda_out)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+        double c = 0.5 * ((hi[k] + fe[k]) - (hj[k] - fe[k]));
+        fout[k] = c;
+        if (c > 0.0) s += c;
+    }
+    double lambda = 0.0;
+    int binds = 0;
+    if (s > u) {
+        binds = 1;
+        int32_t M = 0;
+        for (int32_t k = 0; k < K; ++k)
+            if (fout[k] > 0.0) work[M++] = fout[k];
+        qsort(work, (size_t)M, sizeof(double), cmp_desc);
+        double sum_c = 0.0, best = 0.0;
+        int found = 0;
+        for (int32_t p = 1; p <= M; ++p) {
+            sum_c += work[p - 1];
+            const double cand = (sum_c - u) / (double)p;
+            const double lower = (p < M) ? work[p] : 0.0;
+            if (lower <= cand && cand <= work[p - 1]) {
+                lambda = cand;
+                found = 1;
+                break;
+            }
+            if (work[p - 1] >= cand) best = cand;  /* rounding fallback: largest p with c_(p) >= lambda_p */
+        }
+        if (!found) lambda = best;
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        double v = fout[k] - lambda;
+        fout[k] = v > 0.0 ? v : 0.0;
+    }
+    *lambda_out = lambda;
+    return binds;
+}
+
 /* One AGD edge step (Algorithm 3, inner loop) for one arc with pre-update
  * congestion psi = max(0, F - u). Updates fout (= new flows) and *beta.
  * Returns 1 if the step was accepted. */
@@ -335,7 +388,8 @@ typedef struct {
 
 /*
  * Algorithm 1 (method ORC_ESO), Algorithm 3 (ORC_AGD) or Algorithm 4 (ORC_GDM),
- * resumable.
+ * or the same loop with the capacity-enforcing edge step of Section 6's
+ * formulation (ORC_CAP, orc_cap_edge), resumable.
  *
  * State in/out: f (m*K), beta (m, AGD/GDM), v (m*K, GDM velocities; else may
  * be NULL), *t (iteration counter), *z_prev (previous objective, +inf at the
@@ -393,6 +447,9 @@ int64_t orc_run(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col
                 if (method == ORC_ESO) {
                     double ps, r;
                     orc_eso_edge(K, hi, hj, fe, u[e], fo, work, &ps, &r);
+                } else if (method == ORC_CAP) {
+                    double lam;
+                    orc_cap_edge(K, hi, hj, fe, u[e], fo, work, &lam);
                 } else if (method == ORC_GDM) {
                     orc_gdm_edge(K, hi, hj, fe, v + (size_t)e * K, F[e], u[e], psi[e], tt, &beta[e],
                                  beta_min, prm->beta_max, prm->alpha_inc, prm->alpha_dec,

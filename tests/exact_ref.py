@@ -11,9 +11,13 @@ here runs in Python ``fractions.Fraction`` arithmetic on tiny inputs:
   Algorithm 2).
 * ``edge_objective``: the subproblem objective of Expression 13 (edge
   subproblem in the step variable, slack r minimised out).
-* ``exact_pdr``: PDR-ESO / PDR-AGD sweeps from the definitions (excess by
-  in/out arc lists, QP by ``qp_threshold``, AGD accept test by a direct
+* ``exact_pdr``: PDR-ESO / AGD / GDM sweeps and the capacity-enforcing loop
+  from the definitions (excess by in/out arc lists, QP by ``qp_threshold``,
+  capped-simplex projection by ``cap_threshold``, AGD accept test by a direct
   difference of ``edge_objective``).
+* ``cap_bruteforce`` / ``cap_threshold``: the capacity-enforcing edge step
+  (projection onto {f >= 0, sum f <= u}) by support enumeration and by
+  threshold iteration.
 * ``lp_feasible``: feasibility of the constraint system of Section 1 by a
   Bland's-rule phase-1 simplex in exact arithmetic.
 """
@@ -94,6 +98,56 @@ def qp_threshold(c: Sequence, u) -> tuple:
     return [max(ZERO, x - psi / 2) for x in c], psi
 
 
+def cap_objective(fn, c) -> Fr:
+    return sum(((a - b) * (a - b) for a, b in zip(fn, c)), ZERO)
+
+
+def cap_bruteforce(c: Sequence, u) -> tuple:
+    """Exact projection of c onto {f >= 0, sum f <= u} (the capacity-enforcing
+    edge step of Section 6's formulation) by enumerating supports A: the free
+    candidate f = c on A, and the capped one f = c - lam on A with
+    lam = (sum_A c - u) / |A| >= 0; feasible candidates are compared by
+    sum (f - c)^2. Returns (f_new, lam)."""
+    c = [fr(x) for x in c]
+    u = fr(u)
+    K = len(c)
+    best = None
+    for size in range(K + 1):
+        for A in combinations(range(K), size):
+            cand = [c[k] if k in A else ZERO for k in range(K)]
+            if all(cand[k] > 0 for k in A) and sum(cand, ZERO) <= u:
+                val = cap_objective(cand, c)
+                if best is None or val < best[0]:
+                    best = (val, cand, ZERO)
+            if size:
+                lam = (sum((c[k] for k in A), ZERO) - u) / size
+                if lam >= 0:
+                    cand = [c[k] - lam if k in A else ZERO for k in range(K)]
+                    if all(cand[k] > 0 for k in A):
+                        val = cap_objective(cand, c)
+                        if best is None or val < best[0]:
+                            best = (val, cand, lam)
+    return best[1], best[2]
+
+
+def cap_threshold(c: Sequence, u) -> tuple:
+    """The same projection by Michelot's threshold iteration: A = {c > 0}; if
+    sum_A c <= u the capacity is slack; else repeat lam = (sum_A c - u)/|A|,
+    A <- {k in A: c_k > lam} until A is unchanged."""
+    c = [fr(x) for x in c]
+    u = fr(u)
+    A = [k for k in range(len(c)) if c[k] > 0]
+    if sum((c[k] for k in A), ZERO) <= u:
+        return [x if x > 0 else ZERO for x in c], ZERO
+    while True:
+        lam = (sum((c[k] for k in A), ZERO) - u) / len(A)
+        A2 = [k for k in A if c[k] > lam]
+        if A2 == A or not A2:  # empty only when u = 0 and A's values all equal lam
+            break
+        A = A2
+    return [max(ZERO, x - lam) for x in c], lam
+
+
 # --------------------------------------------------------------- instances
 class ExactInstance:
     """Instance data as Fractions with in/out arc lists per vertex."""
@@ -165,8 +219,8 @@ def edge_objective(F, dfs, hi, hj, u) -> Fr:
 
 
 def exact_pdr(ex: ExactInstance, method: str, T: int, params=None):
-    """T passes of Algorithm 1 ('eso'), Algorithm 3 ('agd') or Algorithm 4 ('gdm')
-    from f = 0 (and zero velocities).
+    """T passes of Algorithm 1 ('eso'), Algorithm 3 ('agd'), Algorithm 4 ('gdm') or
+    the capacity-enforcing loop ('cap') from f = 0 (and zero velocities).
 
     Returns (f, list of z values before each update)."""
     K, m = ex.K, ex.m
@@ -185,9 +239,9 @@ def exact_pdr(ex: ExactInstance, method: str, T: int, params=None):
         fn = []
         for e in range(m):
             i, j = ex.tail[e], ex.head[e]
-            if method == "eso":
+            if method in ("eso", "cap"):
                 c = [(h[i][k] - h[j][k]) / 2 + f[e][k] for k in range(K)]
-                new, _ = qp_threshold(c, ex.u[e])
+                new, _ = (qp_threshold if method == "eso" else cap_threshold)(c, ex.u[e])
                 fn.append(new)
             else:
                 F = sum(f[e], ZERO)

@@ -15,8 +15,8 @@ import pytest
 
 import oracle
 from conftest import make_instance
-from exact_ref import (ExactInstance, edge_objective, exact_pdr, lp_feasible, qp_bruteforce,
-                       qp_threshold)
+from exact_ref import (ExactInstance, cap_bruteforce, cap_threshold, edge_objective, exact_pdr,
+                       lp_feasible, qp_bruteforce, qp_threshold)
 from gen.instance import recipe_grid4_k8, recipe_small
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -198,12 +198,13 @@ def test_potential_difference_is_negative_gradient():
 
 # ------------------------------------------------------------------ P5: worked closed forms
 @pytest.mark.parametrize("name", ["eso_infeasible", "eso_feasible", "agd_feasible", "agd_reject",
-                                  "gdm_feasible"])
+                                  "gdm_feasible", "cap_infeasible", "cap_feasible"])
 def test_two_vertex_worked_examples(name):
     """P5: the oracle reproduces the hand-derived trajectories in tests/golden/two_vertex.txt."""
     g = read_golden("two_vertex.txt")[name]
     inst = two_vertex(float(g["d"]), float(g["u"]), g["K"])
-    method = {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM}[g["method"]]
+    method = {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM,
+              "cap": oracle.CAP}[g["method"]]
     st = oracle.State(inst, method)
     for step, expect in enumerate(g["flows"]):
         st.run(1)
@@ -268,14 +269,15 @@ def test_agd_objective_change_is_exact_subproblem_difference():
 
 
 # ------------------------------------------------------------------ P4: exact sweeps
-@pytest.mark.parametrize("method", ["eso", "agd", "gdm"])
+@pytest.mark.parametrize("method", ["eso", "agd", "gdm", "cap"])
 def test_oracle_matches_exact_rational_sweeps(grid4, method):
     """P4: 60 sweeps in exact rationals (independent code: threshold QP, in/out arc
     lists, direct subproblem differences) match the FP64 oracle to 1e-12 max(u)."""
     inst = grid4
     ex = ExactInstance.from_instance(inst)
     f_ex, z_ex = exact_pdr(ex, method, 60)
-    st, zs = oracle.run(inst, {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM}[method], 60)
+    st, zs = oracle.run(inst, {"eso": oracle.ESO, "agd": oracle.AGD, "gdm": oracle.GDM,
+                               "cap": oracle.CAP}[method], 60)
     f_ex = np.array([[float(x) for x in row] for row in f_ex])
     tol = 1e-12 * float(np.max(inst.u))
     assert np.max(np.abs(st.f - f_ex)) <= tol
@@ -283,7 +285,7 @@ def test_oracle_matches_exact_rational_sweeps(grid4, method):
 
 
 # ------------------------------------------------------------------ P6: monotone z
-@pytest.mark.parametrize("method", [oracle.ESO, oracle.AGD])
+@pytest.mark.parametrize("method", [oracle.ESO, oracle.AGD, oracle.CAP])
 @pytest.mark.parametrize("kind,size,K,seed", [("grid", 4, 8, 1), ("knn", 40, 30, 2),
                                               ("grid", 5, 20, 3)])
 def test_objective_monotone(method, kind, size, K, seed):
@@ -566,3 +568,67 @@ def test_violation_bounds_follow_from_z():
         assert rep["max_abs_excess"] == pytest.approx(float(np.abs(Delta).max()), rel=1e-14, abs=0)
         assert psi.max() <= math.sqrt(2 * z) * (1 + 1e-12)
         assert np.all(np.abs(Delta) <= np.sqrt(2 * z * deg)[:, None] * (1 + 1e-12))
+
+
+# ------------------------------------------------------------------ capacity-enforcing loop (Section 6)
+def test_cap_edge_matches_exact_projection():
+    """The capacity-enforcing edge step equals the exact projection onto
+    {f >= 0, sum f <= u} found by support enumeration, which equals the
+    threshold iteration."""
+    rng = random.Random(21)
+    for _ in range(300):
+        K = rng.randint(1, 7)
+        c, u = _rand_qp(rng, K)
+        ref, _ = cap_bruteforce(c, u)
+        thr, lam = cap_threshold(c, u)  # lam: the smallest multiplier (unique unless u = 0)
+        assert ref == thr
+        hi, hj, fe = _qp_inputs_from_c(c)
+        out, lam_o, binds = oracle.cap_edge([float(x) for x in hi], [float(x) for x in hj],
+                                            [float(x) for x in fe], float(u))
+        scale = max(1.0, float(u), max(abs(float(x)) for x in c))
+        assert np.max(np.abs(out - np.array([float(x) for x in ref]))) <= 1e-13 * scale
+        assert abs(lam_o - float(lam)) <= 1e-13 * scale
+        assert binds == (sum((x for x in c if x > 0), Fr(0)) > u)
+
+
+def test_cap_keeps_every_capacity():
+    """Starting from f = 0 the loop never exceeds a capacity (each edge step is a
+    projection onto the arc's capacity set) beyond the rounding of the sum, so
+    the congestion term stays at the rounding level."""
+    inst = recipe_small("knn", 40, 30, seed=2, u_range=(1, 4), d_range=(2, 9))
+    st = oracle.State(inst, oracle.CAP)
+    for _ in range(20):
+        st.run(10)
+        F, psi = oracle.congestion(inst, st.f)
+        assert np.any(F >= inst.u * (1 - 1e-12))  # capacities do bind
+        assert np.all(F <= inst.u * (1 + 1e-14))
+        assert np.all(psi <= 1e-14 * inst.u)
+
+
+def test_cap_fixed_point_meets_the_pipe_pressure_conditions():
+    """Section 6's KKT conditions at convergence, with gamma_e the pipe pressure
+    (0 on an unsaturated arc): a used commodity has h_i - h_j = gamma_e (so 0 on
+    an unsaturated arc, and the same value for every used commodity of a
+    saturated arc); an unused one has h_i - h_j <= gamma_e."""
+    inst = recipe_small("grid", 4, 6, seed=5, u_range=(1, 3), d_range=(2, 6))
+    st, zs = oracle.run(inst, oracle.CAP, 20000, eps_obj=1e-15)
+    rep = oracle.report(inst, st.f)
+    assert rep["z"] > 1e-3 and rep["verdict"] == "infeasible"  # capacities bind
+    _, h = oracle.excess(inst, st.f)
+    F, _ = oracle.congestion(inst, st.f)
+    tails = inst.tails()
+    tol = 1e-5 * float(np.max(np.abs(h)))
+    saturated = 0
+    for e in range(inst.m):
+        diff = h[tails[e]] - h[inst.col[e]]
+        used = st.f[e] > 1e-9 * float(np.max(inst.d))
+        sat = F[e] >= inst.u[e] * (1 - 1e-9)
+        if sat:
+            saturated += 1
+            gamma = float(diff[used].max()) if used.any() else max(0.0, float(diff.max()))
+            assert gamma >= -tol
+        else:
+            gamma = 0.0
+        assert np.all(np.abs(diff[used] - gamma) <= tol), e
+        assert np.all(diff[~used] <= gamma + tol), e
+    assert saturated > 0
