@@ -44,7 +44,12 @@ typedef enum {
     PDR_ERR_NUMERIC = 5  /* the objective became non-finite */
 } pdr_status;
 
-typedef enum { PDR_ESO = 0, PDR_AGD = 1, PDR_GDM = 2 } pdr_method;
+/* PDR_ESO: Algorithm 1 with the exact edge subproblem (Algorithm 2);
+ * PDR_AGD: Algorithm 3; PDR_GDM: Algorithm 4; PDR_CAP: the loop of Algorithm 1
+ * for Section 6's formulation (conservation relaxed, capacities kept): each arc
+ * projects c = ((h_i + f) - (h_j - f))/2 onto {f >= 0, sum_k f <= u}, i.e.
+ * f' = max(0, c - lambda) with lambda = 0 when sum max(0, c) <= u. */
+typedef enum { PDR_ESO = 0, PDR_AGD = 1, PDR_GDM = 2, PDR_CAP = 3 } pdr_method;
 
 /* PDR_FP64: f and h stored and updated in FP64.
  * PDR_FP32_BULK: f and h stored and updated in FP32; excess accumulation,

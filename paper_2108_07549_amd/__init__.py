@@ -25,7 +25,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdr.so")
 
-ESO, AGD, GDM = 0, 1, 2
+ESO, AGD, GDM, CAP = 0, 1, 2, 3
 FP64, FP32_BULK = 0, 1
 VERDICT = {0: "undecided", 1: "feasible", 2: "infeasible"}
 STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVICE",

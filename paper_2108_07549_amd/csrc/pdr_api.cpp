@@ -111,7 +111,7 @@ Tiling auto_tiling(int32_t Kp, int32_t precision, int32_t method)
     if (L > kMaxLanes) L = kMaxLanes;
     // the gradient steps reduce once per arc (no threshold passes): they run
     // best with at most 512 lanes and more vectors per lane
-    if (method != PDR_ESO && L > 512 && cover_nv(nvec, 512) > 0) L = 512;
+    if ((method == PDR_AGD || method == PDR_GDM) && L > 512 && cover_nv(nvec, 512) > 0) L = 512;
     int nv = cover_nv(nvec, L);
     if (nv < 1) nv = pow2ceil((nvec + L - 1) / L);
     return Tiling{L, nv};
@@ -308,8 +308,9 @@ hipError_t enqueue_passes(pdr_ctx *c, int64_t count, hipStream_t st)
         hipError_t e = pdr::launch_height(c->g, fp64, f, h, c->zpart, c->Fsum, c->ctrl, c->zlog,
                                           c->zlog_cap - 1, st);
         if (e == hipSuccess)
-            e = c->method == PDR_ESO
-                    ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, st)
+            e = c->method == PDR_ESO || c->method == PDR_CAP
+                    ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl,
+                                      c->method == PDR_CAP, st)
                     : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm, c->ctrl,
                                       c->method == PDR_GDM ? cur_v(c) : nullptr, st);
         if (e != hipSuccess) return e;
@@ -456,7 +457,8 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
             return invalid("commodity endpoint has degree 0 (its height is undefined)");
     }
     // ---- options
-    if (opt.method != PDR_ESO && opt.method != PDR_AGD && opt.method != PDR_GDM)
+    if (opt.method != PDR_ESO && opt.method != PDR_AGD && opt.method != PDR_GDM &&
+        opt.method != PDR_CAP)
         return invalid("unknown method");
     if (opt.precision != PDR_FP64 && opt.precision != PDR_FP32_BULK)
         return invalid("unknown precision");
@@ -781,8 +783,9 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
                                          c->stream);
             if (err == hipSuccess) err = hipEventRecord(ev[q][1], c->stream);
             if (err == hipSuccess)
-                err = c->method == PDR_ESO
-                          ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl, c->stream)
+                err = c->method == PDR_ESO || c->method == PDR_CAP
+                          ? pdr::launch_eso(c->g, fp64, c->tiling, f, h, c->Fsum, c->ctrl,
+                                            c->method == PDR_CAP, c->stream)
                           : pdr::launch_agd(c->g, fp64, c->tiling, f, h, c->Fsum, c->beta, prm,
                                             c->ctrl, c->method == PDR_GDM ? cur_v(c) : nullptr,
                                             c->stream);
@@ -1128,7 +1131,7 @@ pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
                 double *nxt = seg[(size_t)k];
                 PDR_CHECK(c, hipMemcpyAsync(nxt, prev, mK * 8, hipMemcpyDeviceToDevice, c->stream));
                 PDR_CHECK(c, pdr::launch_eso(c->g, true, c->tiling, nxt, hseg[(size_t)k], c->Fsum,
-                                             c->ctrl, c->stream));
+                                             c->ctrl, false, c->stream));
                 prev = nxt;
             }
         }

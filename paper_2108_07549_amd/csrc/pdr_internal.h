@@ -88,8 +88,9 @@ hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, d
                          hipStream_t st);
 hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, double *h64,
                                double *zpart, double *maxpart, hipStream_t st);
+// ESO arc update (Expression 14); cap: the capacity-enforcing step instead.
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
-                      double *Fsum, const Ctrl *ctrl, hipStream_t st);
+                      double *Fsum, const Ctrl *ctrl, bool cap, hipStream_t st);
 // AGD arc update (Algorithm 3); with a velocity buffer vel, the GDM update
 // (Algorithm 4).
 hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
@@ -129,7 +130,8 @@ hipError_t launch_bbegin(const InstView *views, int B, double eps_obj, double z_
                          hipStream_t st);
 hipError_t launch_bheight(const InstView *views, int B, const int2 *hmap, int64_t nblocks,
                           bool fp64, int unroll, hipStream_t st);
-// method: 0 ESO, 1 AGD, 2 GDM; blocks of `amap` hold ArcShape(tl.lanes) groups.
+// method: 0 ESO, 1 AGD, 2 GDM, 3 capacity-enforcing; blocks of `amap` hold
+// ArcShape(tl.lanes) groups.
 hipError_t launch_barc(int method, const InstView *views, const int2 *amap, int64_t nblocks,
                        bool fp64, Tiling tl, hipStream_t st);
 // Number of instances whose stop test has fired (written to device *out).

@@ -467,7 +467,12 @@ struct ArcShape {
 // simplex: with A = {k: c_k > 0}, repeat psi = (sum_A c - u) / (1 + |A|/2),
 // A <- {k in A: c_k > psi/2} until A is unchanged. Each pass is one group
 // reduction of (sum, count) over the register-resident c.
-template <typename T, int L, int NV>
+// CAP: the capacity-enforcing step of Section 6's formulation instead (no
+// congestion term, sum f' <= u kept): f'_k = max(0, c_k - lambda), the
+// projection of c onto {f >= 0, sum f <= u}, with lambda = (sum_A c - u)/|A|
+// found by the same iteration; at u = 0 the set can empty (every c equal to
+// lambda), which also ends it.
+template <typename T, int L, int NV, bool CAP = false>
 __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, int64_t slot, int lane, double *lds)
 {
     constexpr int V = VecT<T>::N;
@@ -506,12 +511,12 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
     }
     group_sum<L, 2>(red, lds, phase);
     double Ssum = red[0], P = red[1];
-    double psi = 0.0;
+    double half = 0.0;  // psi/2 (ESO) or lambda (CAP): the shift of the active c
     if (Ssum > u) {
         double theta = 0.0;
         for (;;) {
-            psi = (Ssum - u) / (1.0 + 0.5 * P);
-            const double th = fmax(theta, 0.5 * psi);
+            half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
+            const double th = fmax(theta, half);
             double r2[2] = {0.0, 0.0};
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -524,13 +529,13 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
                     }
                 }
             group_sum<L, 2>(r2, lds, phase);
-            if (r2[1] == P) break;  // active set unchanged: psi is the root
+            // active set unchanged: the shift is the root
+            if (r2[1] == P || (CAP && r2[1] == 0.0)) break;
             Ssum = r2[0];
             P = r2[1];
             theta = th;
         }
     }
-    const double half = 0.5 * psi;
     double fs[1] = {0.0};
     T *fo = f + e * Kp;
 #pragma unroll
@@ -551,7 +556,7 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
     if (lane == 0) Fsum[e] = fs[0];
 }
 
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool CAP>
 __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restrict__ f,
                                                           const T *__restrict__ h,
                                                           double *__restrict__ Fsum,
@@ -565,11 +570,11 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    eso_arc<T, L, NV>(g, f, h, Fsum, slot, lane, lds);
+    eso_arc<T, L, NV, CAP>(g, f, h, Fsum, slot, lane, lds);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool CAP>
 __global__ __launch_bounds__(ArcShape<L>::BS) void kb_eso(const InstView *__restrict__ views,
                                                           const int2 *__restrict__ amap)
 {
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void kb_eso(const InstView *__rest
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = (int64_t)it.y * S::GPB + grp;
     if (L <= 64 && slot >= I.g.m) return;
-    eso_arc<T, L, NV>(I.g, (T *)I.f, (const T *)I.h, I.Fsum, slot, lane, lds);
+    eso_arc<T, L, NV, CAP>(I.g, (T *)I.f, (const T *)I.h, I.Fsum, slot, lane, lds);
 }
 
 // PDR-AGD arc update (Algorithm 3): phi_k = h_ik - h_jk - psi,
@@ -1099,18 +1104,25 @@ static inline unsigned arc_blocks(int64_t m, int L)
 }
 
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
-                      double *Fsum, const Ctrl *ctrl, hipStream_t st)
+                      double *Fsum, const Ctrl *ctrl, bool cap, hipStream_t st)
 {
     if (g.m == 0) return hipSuccess;
 #define PDR_ESO_CASE(L_, NV_)                                                                    \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
         const unsigned nb = arc_blocks(g.m, L_);                                                 \
         constexpr int BS = L_ > 64 ? L_ : 256;                                                   \
-        if (fp64)                                                                                \
-            k_eso<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h, Fsum,   \
-                                                      ctrl);                                     \
+        if (fp64 && !cap)                                                                        \
+            k_eso<double, L_, NV_, false><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h,  \
+                                                             Fsum, ctrl);                        \
+        else if (fp64)                                                                           \
+            k_eso<double, L_, NV_, true><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h,   \
+                                                            Fsum, ctrl);                         \
+        else if (!cap)                                                                           \
+            k_eso<float, L_, NV_, false><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h,     \
+                                                            Fsum, ctrl);                         \
         else                                                                                     \
-            k_eso<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h, Fsum, ctrl); \
+            k_eso<float, L_, NV_, true><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h,      \
+                                                           Fsum, ctrl);                          \
         return hipGetLastError();                                                                \
     }
     PDR_TILINGS(PDR_ESO_CASE)
@@ -1538,9 +1550,13 @@ hipError_t launch_barc(int method, const InstView *views, const int2 *amap, int6
     if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
         constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
         if (method == 0 && fp64)                                                               \
-            kb_eso<double, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                           \
+            kb_eso<double, L_, NV_, false><<<nb, BS, 0, st>>>(views, amap);                    \
         else if (method == 0)                                                                  \
-            kb_eso<float, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                            \
+            kb_eso<float, L_, NV_, false><<<nb, BS, 0, st>>>(views, amap);                     \
+        else if (method == 3 && fp64)                                                          \
+            kb_eso<double, L_, NV_, true><<<nb, BS, 0, st>>>(views, amap);                     \
+        else if (method == 3)                                                                  \
+            kb_eso<float, L_, NV_, true><<<nb, BS, 0, st>>>(views, amap);                      \
         else if (method == 1 && fp64)                                                          \
             kb_agd<double, L_, NV_><<<nb, BS, 0, st>>>(views, amap);                           \
         else if (method == 1)                                                                  \

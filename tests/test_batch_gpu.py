@@ -19,7 +19,7 @@ from gen.instance import recipe_grid4_k8, recipe_small
 pytestmark = pytest.mark.gpu
 
 METHODS = {"eso": (pdr.ESO, oracle.ESO), "agd": (pdr.AGD, oracle.AGD),
-           "gdm": (pdr.GDM, oracle.GDM)}
+           "gdm": (pdr.GDM, oracle.GDM), "cap": (pdr.CAP, oracle.CAP)}
 
 
 def say(*a):

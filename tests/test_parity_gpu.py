@@ -18,7 +18,7 @@ from gen.instance import MissingLoadFactor, load_instance, recipe_grid4_k8, reci
 pytestmark = pytest.mark.gpu
 
 METHODS = {"eso": (pdr.ESO, oracle.ESO), "agd": (pdr.AGD, oracle.AGD),
-           "gdm": (pdr.GDM, oracle.GDM)}
+           "gdm": (pdr.GDM, oracle.GDM), "cap": (pdr.CAP, oracle.CAP)}
 ALL = list(METHODS)
 
 
@@ -69,8 +69,11 @@ def test_grid4_k8_500_sweeps(method):
     _, ho = oracle.excess(inst, r["st"].f)
     assert np.max(np.abs(r["hg"] - ho)) <= tol
     assert r["res"]["sweeps_done"] == 500 and r["res"]["evaluations"] == 500
-    if method != "eso":
+    if method in ("agd", "gdm"):
         assert np.array_equal(r["bg"], r["st"].beta)
+    if method == "cap":  # capacities hold up to the rounding of a row sum
+        F = r["fg"].sum(axis=1)
+        assert np.all(F <= inst.u * (1 + 1e-14))
 
 
 def test_residual_report_matches_oracle():
