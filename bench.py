@@ -251,7 +251,8 @@ def main():
         for name, meth, prec in (("agd_fp64", pdr.AGD, pdr.FP64), ("gdm_fp64", pdr.GDM, pdr.FP64),
                                  ("eso_fp32", pdr.ESO, pdr.FP32_BULK),
                                  ("agd_fp32", pdr.AGD, pdr.FP32_BULK),
-                                 ("gdm_fp32", pdr.GDM, pdr.FP32_BULK)):
+                                 ("gdm_fp32", pdr.GDM, pdr.FP32_BULK),
+                                 ("cap_fp64", pdr.CAP, pdr.FP64)):
             r = time_variant(pdr, inst, meth, prec, args.steps, args.warmup)
             print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
             var[name] = dict(updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"],

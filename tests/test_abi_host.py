@@ -140,3 +140,15 @@ def test_batch_and_adjoint_null_handles_are_invalid():
     z = C.c_double()
     assert L.pdr_adjoint(None, 1, 0, C.byref(z), None, None) == 1
     L.pdr_batch_destroy(None)  # ignored
+
+
+def test_autograd_function_checks_dtypes_before_any_call():
+    """The torch.autograd.Function over pdr_adjoint takes float64 u and d and
+    refuses others before it reaches the library."""
+    torch = pytest.importorskip("torch")
+    from gen.instance import recipe_grid4_k8
+    from paper_2108_07549_amd.autograd import residual_after_sweeps
+    inst = recipe_grid4_k8()
+    with pytest.raises(TypeError):
+        residual_after_sweeps(inst, torch.tensor(inst.u, dtype=torch.float32),
+                              torch.tensor(inst.d, dtype=torch.float64), 4)

@@ -103,3 +103,70 @@ def test_grid100_k10000_sampled_coordinates():
         say("grid100 coordinate", j, got, zdot)
         assert z == pytest.approx(zo, rel=1e-10)
         assert abs(got - zdot) <= 1e-9 * max(abs(zdot), 1e-12 * abs(zo))
+
+
+AUTOGRAD_CHILD = r"""
+import sys
+sys.path.insert(0, {root!r})
+import torch  # first, so that the library shares torch's HIP runtime
+import dataclasses
+import numpy as np
+import paper_2108_07549_amd as pdr
+from paper_2108_07549_amd.autograd import residual_after_sweeps
+from gen.instance import recipe_grid4_k8
+
+base = recipe_grid4_k8()
+heavy = dataclasses.replace(base, d=base.d * 20.0)
+# (name, instance, T, checkpoint, central-difference tolerance relative to the
+# largest gradient entry). grid4_k8 after 256 passes is nearly converged
+# (z ~ 7e-13): rounding of the flows (~1e-16 relative) moves z by ~1e-22, which
+# is ~1e-3 of the largest gradient times 2h, so its tolerance is 1e-2; the
+# congested instance's differences are clean to 1e-5.
+for name, inst, T, C, tol in (("grid4_k8", base, 256, 16, 1e-2),
+                              ("grid4_k8 x20", heavy, 64, 16, 1e-5)):
+    for dev in ("cpu", "cuda"):
+        u = torch.tensor(inst.u, dtype=torch.float64, device=dev, requires_grad=True)
+        d = torch.tensor(inst.d, dtype=torch.float64, device=dev, requires_grad=True)
+        z = residual_after_sweeps(inst, u, d, T, C)
+        assert z.device.type == dev and z.dtype == torch.float64
+        (3.0 * z).backward()
+        with pdr.Context.from_instance(inst, method=pdr.ESO) as c:
+            z0, gu0, gd0 = c.adjoint(T, C)
+        assert z.item() == z0, (name, dev)
+        assert np.array_equal(u.grad.cpu().numpy(), 3.0 * gu0), (name, dev)
+        assert np.array_equal(d.grad.cpu().numpy(), 3.0 * gd0), (name, dev)
+    # central differences, h = 1e-6, over every coordinate (m + K = 56)
+    h = 1e-6
+    scale = max(np.abs(gu0).max(), np.abs(gd0).max())
+    worst = 0.0
+    for j in range(inst.m + inst.K):
+        vals = []
+        for sgn in (1.0, -1.0):
+            uu = torch.tensor(inst.u, dtype=torch.float64)
+            dd = torch.tensor(inst.d, dtype=torch.float64)
+            if j < inst.m:
+                uu[j] += sgn * h
+            else:
+                dd[j - inst.m] += sgn * h
+            vals.append(residual_after_sweeps(inst, uu, dd, T, C).item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        g = gu0[j] if j < inst.m else gd0[j - inst.m]
+        worst = max(worst, abs(fd - g) / scale)
+    print(name, "T", T, "worst central-difference error / scale", worst, flush=True)
+    assert worst <= tol, (name, worst)
+print("autograd ok", flush=True)
+"""
+
+
+def test_autograd_function_and_central_differences():
+    """ResidualAfterSweeps (torch.autograd.Function over pdr_adjoint) on CPU and
+    device tensors equals the C ABI's adjoint exactly; its gradient agrees with
+    central differences of its own forward pass. torch is imported before the
+    library in a child process so both use one HIP runtime."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", AUTOGRAD_CHILD.format(root=root)],
+                       capture_output=True, text=True, timeout=600)
+    say(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0 and "autograd ok" in r.stdout
