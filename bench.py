@@ -106,6 +106,28 @@ def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=200):
                 precision_final="fp64" if n64 or precision == pdr.FP64 else "fp32")
 
 
+def time_to_target(pdr, inst, method, precision, target, cap, window=512):
+    """From f = 0, pdr_solve to z <= target (FP32-bulk runs widen to FP64 and
+    polish by its rule) in one call; the wall time, the passes in each
+    precision, and the first pass at which z fell to each decade of a ladder."""
+    with pdr.Context.from_instance(inst, method=method, precision=precision) as ctx:
+        pdr.device_synchronize()
+        t0 = time.perf_counter()
+        n32, n64 = ctx.solve(target, cap, window)
+        pdr.device_synchronize()
+        sec = time.perf_counter() - t0
+        res = ctx.residual()
+        ev = res["evaluations"]
+        first = max(0, ev - (1 << 20))  # the z log keeps the last 2^20 evaluations
+        zl = ctx.z_log(first, ev - first)
+    ladder = {}
+    for thr in (1e-2, 1e-4, 1e-6, 1e-8):
+        hit = np.nonzero(zl <= thr)[0]
+        ladder[str(thr)] = int(first + hit[0]) if hit.size else None
+    return dict(seconds=sec, sweeps_fp32=n32, sweeps_fp64=n64, z_final=res["z"],
+                reached=bool(res["z"] <= target), verdict=res["verdict"], first_pass_at=ladder)
+
+
 def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
     """Batched sweeps of the uneven B-instance recipe: wall-clock updates/s of
     plain sweeps (graph replays) before and after the tiling autotuner, and the
@@ -193,6 +215,13 @@ def main():
                     help="skip the adjoint (reverse-mode gradient) timing")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
+    ap.add_argument("--ttr-workload", default="",
+                    help="also run FP64 and FP32 bulk + FP64 polish to z <= 1e-8 on this "
+                         "workload (e.g. knn2500_k1000; about a minute per method)")
+    ap.add_argument("--ttr-methods", default="eso,gdm",
+                    help="methods of --ttr-workload (eso, agd, gdm, cap)")
+    ap.add_argument("--ttr-cap", type=int, default=2_000_000,
+                    help="pass limit of each --ttr-workload run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -267,6 +296,19 @@ def main():
             ttr[name] = r
         out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
                                        target=1e-8, **ttr)
+    if args.ttr_workload:
+        tinst = load_instance(args.ttr_workload)
+        full = dict(workload=args.ttr_workload, target=1e-8, cap=args.ttr_cap)
+        names = {"eso": pdr.ESO, "agd": pdr.AGD, "gdm": pdr.GDM, "cap": pdr.CAP}
+        for mname in [x for x in args.ttr_methods.split(",") if x]:
+            for pname, prec in (("fp64", pdr.FP64), ("fp32_polish", pdr.FP32_BULK)):
+                print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: running", file=sys.stderr,
+                      flush=True)
+                r = time_to_target(pdr, tinst, names[mname], prec, 1e-8, args.ttr_cap)
+                print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: {r}", file=sys.stderr,
+                      flush=True)
+                full[f"{mname}_{pname}"] = r
+        out["time_to_residual_full"] = full
     if not args.no_adjoint:
         r = time_adjoint(pdr, inst, 8, 4, head["ms_per_step"])
         print(f"[bench] adjoint T=8: {r['ms_per_pass']:.3f} ms per pass "
