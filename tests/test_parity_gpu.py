@@ -140,6 +140,37 @@ def test_ragged_commodity_counts(method, K):
     assert np.allclose(r["zg"], r["zo"], rtol=1e-9, atol=1e-13 * r["zo"][0])
 
 
+@pytest.mark.parametrize("method", ALL)
+def test_longest_supported_commodity_row_fp64(method):
+    """K = 40,960, the longest FP64 row an arc kernel holds (1024 lanes x 20
+    vectors of two commodities), on a congested 210-point k-NN graph."""
+    gm, om = METHODS[method]
+    inst = recipe_small("knn", 210, 40960, seed=77, u_range=(50, 4000), d_range=(1, 5))
+    T = 8
+    with ctx_for(inst, gm) as c:
+        assert c.tiling() == (1024, 20, 40960)
+        c.sweep(T)
+        f = c.flows()
+        zg = c.z_log(0, T)
+    st, zo = oracle.run(inst, om, T)
+    assert np.max(np.abs(f - st.f)) <= flow_tol(inst)
+    assert np.allclose(zg, zo, rtol=1e-9, atol=0)
+
+
+def test_longest_supported_commodity_row_fp32():
+    """K = 81,920, the longest FP32-bulk row (1024 lanes x 20 vectors of four)."""
+    inst = recipe_small("knn", 300, 81920, seed=78, u_range=(50, 8000), d_range=(1, 5))
+    T = 8
+    with ctx_for(inst, pdr.ESO, pdr.FP32_BULK) as c:
+        assert c.tiling() == (1024, 20, 81920)
+        c.sweep(T)
+        f = c.flows()
+        zg = c.z_log(0, T)
+    st, zo = oracle.run(inst, oracle.ESO, T)
+    assert np.max(np.abs(f - st.f)) <= 1e-3 * float(np.max(inst.u))
+    assert np.allclose(zg, zo, rtol=1e-4, atol=0)
+
+
 # ------------------------------------------------------------------ edge cases
 def test_two_vertex_infeasible_closed_form():
     """d = 10 > u = 8 on the two-vertex instance: f -> (d + u)/2 = 9, z* = 1, G = 2."""
