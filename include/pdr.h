@@ -128,7 +128,10 @@ void pdr_default_options(pdr_options *opt);
  * Host arrays are deep-copied; opt may be NULL for the defaults.
  * Errors: PDR_ERR_INVALID for n < 1, m < 0, K < 1, a malformed CSR, a head
  * out of range, a self-loop, u or d negative or non-finite, s or t out of
- * range, s_k == t_k, or a commodity endpoint of degree 0; PDR_ERR_OOM if the
+ * range, s_k == t_k, a commodity endpoint of degree 0, or more commodities
+ * than one arc kernel holds in the requested precision (a row of at most 8,192
+ * vectors of 16 bytes: K <= 16,384 for PDR_FP64, K <= 32,768 for
+ * PDR_FP32_BULK, whose FP64 polish then needs K <= 16,384); PDR_ERR_OOM if the
  * device buffers would not fit; PDR_ERR_DEVICE for a HIP failure. On failure
  * *out is set to NULL.
  */

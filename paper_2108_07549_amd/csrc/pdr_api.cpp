@@ -132,11 +132,13 @@ pdr_status choose_tiling(pdr_ctx *c, int32_t precision, Tiling *out)
                                                     tl.lanes);
     }
     if (!tiling_covers(tl, c->Kp, precision)) {
-        char buf[200];
+        char buf[240];
+        const int mv = pdr::max_tiling_vectors();
         snprintf(buf, sizeof buf,
                  "no supported arc tiling covers K=%d (padded %d) in this precision "
-                 "(lanes %d x vectors %d; at most %d x %d vectors of 16 bytes per arc)",
-                 c->K, c->Kp, tl.lanes, tl.nv, kMaxLanes, kMaxNv);
+                 "(lanes %d x vectors %d; the longest row is %d vectors of 16 bytes: "
+                 "%d commodities in FP64, %d in FP32 bulk)",
+                 c->K, c->Kp, tl.lanes, tl.nv, mv, 2 * mv, 4 * mv);
         c->err = buf;
         return PDR_ERR_INVALID;
     }

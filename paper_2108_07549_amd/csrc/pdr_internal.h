@@ -78,6 +78,8 @@ struct InstView {
 };
 
 bool tiling_supported(int lanes, int nv);
+// Longest row, in 16-byte vectors, that some supported tiling covers.
+int max_tiling_vectors();
 int64_t height_blocks(const DevGraph &g, int elem_bytes);
 
 // Launchers; each returns the launch status.

@@ -1096,6 +1096,16 @@ bool tiling_supported(int lanes, int nv)
     return false;
 }
 
+int max_tiling_vectors()
+{
+    int best = 0;
+#define PDR_MAXV(L_, NV_) \
+    if (L_ * NV_ > best) best = L_ * NV_;
+    PDR_TILINGS(PDR_MAXV)
+#undef PDR_MAXV
+    return best;
+}
+
 static inline unsigned arc_blocks(int64_t m, int L)
 {
     const int BS = L > 64 ? L : 256;

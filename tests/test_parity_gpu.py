@@ -142,30 +142,38 @@ def test_ragged_commodity_counts(method, K):
 
 @pytest.mark.parametrize("method", ALL)
 def test_longest_supported_commodity_row_fp64(method):
-    """K = 40,960, the longest FP64 row an arc kernel holds (1024 lanes x 20
+    """K = 16,384, the longest FP64 row an arc kernel holds (1024 lanes x 8
     vectors of two commodities), on a congested 210-point k-NN graph."""
     gm, om = METHODS[method]
-    inst = recipe_small("knn", 210, 40960, seed=77, u_range=(50, 4000), d_range=(1, 5))
+    inst = recipe_small("knn", 210, 16384, seed=77, u_range=(20, 1600), d_range=(1, 5))
     T = 8
     with ctx_for(inst, gm) as c:
-        assert c.tiling() == (1024, 20, 40960)
+        assert c.tiling() == (1024, 8, 16384)
         c.sweep(T)
         f = c.flows()
         zg = c.z_log(0, T)
     st, zo = oracle.run(inst, om, T)
     assert np.max(np.abs(f - st.f)) <= flow_tol(inst)
     assert np.allclose(zg, zo, rtol=1e-9, atol=0)
+    with pytest.raises(pdr.PdrError) as ei:
+        ctx_for(recipe_small("knn", 210, 16385, seed=77), gm)
+    assert ei.value.status == 1 and "16384 commodities in FP64" in ei.value.message
 
 
 def test_longest_supported_commodity_row_fp32():
-    """K = 81,920, the longest FP32-bulk row (1024 lanes x 20 vectors of four)."""
-    inst = recipe_small("knn", 300, 81920, seed=78, u_range=(50, 8000), d_range=(1, 5))
+    """K = 32,768, the longest FP32-bulk row (1024 lanes x 8 vectors of four);
+    its FP64 polish does not fit one arc kernel and is refused."""
+    inst = recipe_small("knn", 210, 32768, seed=78, u_range=(40, 3200), d_range=(1, 5))
     T = 8
     with ctx_for(inst, pdr.ESO, pdr.FP32_BULK) as c:
-        assert c.tiling() == (1024, 20, 81920)
+        assert c.tiling() == (1024, 8, 32768)
         c.sweep(T)
         f = c.flows()
         zg = c.z_log(0, T)
+        with pytest.raises(pdr.PdrError) as ei:
+            c.set_precision(pdr.FP64)
+        assert ei.value.status == 1
+        assert np.array_equal(c.flows(), f)  # a refused widening leaves the state alone
     st, zo = oracle.run(inst, oracle.ESO, T)
     assert np.max(np.abs(f - st.f)) <= 1e-3 * float(np.max(inst.u))
     assert np.allclose(zg, zo, rtol=1e-4, atol=0)
