@@ -93,6 +93,14 @@ typedef struct {
                               summing: 0 = automatic, 1, 2, 4 or 8 (tuning) */
     int32_t z_log_capacity; /* objective evaluations kept by pdr_z_log: 0 = 2^20,
                                else a power of two up to 2^20 */
+    int32_t cache_policy;  /* cache hints of the pass's flow, velocity and height
+                              traffic: 0 = automatic (ordinary loads and stores
+                              when f, h and v of one pass fit in the 256 MB
+                              Infinity Cache, so they stay resident between
+                              passes; non-temporal otherwise, so the height rows
+                              that neighbouring arcs re-read stay in L2);
+                              1 = ordinary; 2 = non-temporal. Results are the
+                              same bit for bit; batches always stream. */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */

@@ -396,6 +396,7 @@ void pdr_default_options(pdr_options *opt)
     opt->height_blocks = 0;
     opt->height_unroll = 0;
     opt->z_log_capacity = 0;
+    opt->cache_policy = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -484,6 +485,8 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     if (opt.z_log_capacity < 0 || opt.z_log_capacity > pdr::kZLogCap ||
         (opt.z_log_capacity & (opt.z_log_capacity - 1)) != 0)
         return invalid("z_log_capacity must be 0 or a power of two up to 2^20");
+    if (opt.cache_policy < 0 || opt.cache_policy > 2)
+        return invalid("cache_policy must be 0, 1 or 2");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
@@ -508,6 +511,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     c->cluster_size = opt.cluster_size == 0 ? kClusterAuto : opt.cluster_size;
     c->req_height_grid = opt.height_blocks;
     c->req_height_unroll = opt.height_unroll;
+    c->req_cache_policy = opt.cache_policy;
     if (opt.z_log_capacity > 0) c->zlog_cap = opt.z_log_capacity;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
@@ -619,12 +623,31 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     PDR_UP(c->d_d, d, K);
     PDR_UP(c->d_vorder, vorder.data(), n);
     PDR_UP(c->d_aorder, aorder.data(), m);
+    {
+        // incidence lists in visiting order (in-arcs, then out-arcs, each in
+        // ascending id: the summation order of the excess)
+        std::vector<int32_t> vinfo(4 * (size_t)n), vinc(2 * (size_t)m > 0 ? 2 * (size_t)m : 1);
+        int32_t p = 0;
+        for (int32_t pos = 0; pos < n; ++pos) {
+            const int32_t i = vorder[pos];
+            vinfo[4 * (size_t)pos] = i;
+            vinfo[4 * (size_t)pos + 1] = p;
+            vinfo[4 * (size_t)pos + 2] = in_ptr[i + 1] - in_ptr[i];
+            for (int32_t q = in_ptr[i]; q < in_ptr[i + 1]; ++q) vinc[p++] = in_idx[q];
+            for (int32_t e = rp32[i]; e < rp32[i + 1]; ++e) vinc[p++] = e;
+            vinfo[4 * (size_t)pos + 3] = p;
+        }
+        PDR_UP(c->d_vinfo, vinfo.data(), 4 * (size_t)n);
+        PDR_UP(c->d_vinc, vinc.data(), vinc.size());
+    }
 #undef PDR_UP
     c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,
                     c->d_row_ptr, c->d_tails, c->d_heads, c->d_in_ptr, c->d_in_idx,
                     c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
-                    c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder};
+                    c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder,
+                    c->d_vinfo,   c->d_vinc};
     set_height_chunk(c);
+    set_cache_policy(c);
 
     pdr_status st = ensure_buffers(c, c->precision);
     if (st != PDR_OK) return init_fail(c, st, out);
@@ -964,6 +987,17 @@ pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
 }  // extern "C"
 
 namespace pdr_host {
+void set_cache_policy(pdr_ctx *c)
+{
+    const double w = c->precision == PDR_FP64 ? 8.0 : 4.0;
+    double bytes = w * ((double)c->m + (double)c->n) * (double)c->Kp;
+    if (c->method == PDR_GDM) bytes += w * (double)c->m * (double)c->Kp;
+    bool temporal = bytes <= kCacheResidentBytes;
+    if (c->req_cache_policy == 1) temporal = true;
+    if (c->req_cache_policy == 2) temporal = false;
+    c->g.temporal = (temporal && !c->batch_member) ? 1 : 0;
+}
+
 pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
 {
     pdr_status st;
@@ -989,6 +1023,7 @@ pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
     c->precision = precision;
     c->tiling = tl;
     set_height_chunk(c);
+    set_cache_policy(c);
     PDR_CHECK(c, pdr::launch_rowsum(c->g, precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
                                     c->stream));
     PDR_CHECK(c, hipStreamSynchronize(c->stream));

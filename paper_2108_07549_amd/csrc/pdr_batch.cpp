@@ -444,6 +444,7 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
         if (st != PDR_OK)
             return init_fail_b(st, "instance " + std::to_string(i) + ": " + g_init_error);
         b->members[i]->batch_member = true;
+        set_cache_policy(b->members[i]);  // the batch's kernels stream
     }
     e = hipMalloc((void **)&b->d_count, sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_count, sizeof(int32_t), hipHostMallocDefault);

@@ -28,6 +28,9 @@ constexpr int kClusterAuto = 64;
 // FP32 bulk hands over to the FP64 polish once z is within this factor of the
 // estimated FP32 floor z_noise / rate (see pdr_solve).
 constexpr double kFloorFactor = 5.0;
+// Flows + heights (+ velocities) of one pass at or below this size are kept
+// cache-resident (the MI355X Infinity Cache holds 256 MB).
+constexpr double kCacheResidentBytes = 256.0 * 1024.0 * 1024.0;
 }  // namespace pdr_host
 
 
@@ -48,6 +51,7 @@ struct pdr_ctx {
     int32_t cluster_size = 64;             // vertices per locality cluster; 1 = natural order
     int32_t req_height_grid = 0;           // 0 = automatic
     int32_t req_height_unroll = 0;         // 0 = automatic
+    int32_t req_cache_policy = 0;          // 0 = automatic, 1 = ordinary, 2 = non-temporal
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
@@ -57,7 +61,8 @@ struct pdr_ctx {
     // instance arrays (device)
     int32_t *d_row_ptr = nullptr, *d_tails = nullptr, *d_heads = nullptr, *d_in_ptr = nullptr,
             *d_in_idx = nullptr, *d_deg = nullptr, *d_inj_ptr = nullptr, *d_inj_k = nullptr,
-            *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr;
+            *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr,
+            *d_vinfo = nullptr, *d_vinc = nullptr;
     double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
     // run state (device)
     double *f64 = nullptr, *h64 = nullptr, *v64 = nullptr;
@@ -84,4 +89,7 @@ pdr::AgdParams agd_params(const pdr_ctx *c);
 // Switch a context's storage precision (pdr_set_precision without the check
 // that refuses batch members).
 pdr_status set_precision_impl(pdr_ctx *c, int32_t precision);
+// Choose the sweep kernels' cache hints for the current storage precision
+// (batch members always stream).
+void set_cache_policy(pdr_ctx *c);
 }  // namespace pdr_host

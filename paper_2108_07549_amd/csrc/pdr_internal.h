@@ -47,6 +47,16 @@ struct DevGraph {
     const double *d;         // K
     const int32_t *vorder;   // n: order in which the height kernel visits vertices
     const int32_t *aorder;   // m: order in which the arc kernels visit arcs
+    // Incidence lists in visiting order: position p of vorder has
+    // vinfo[4p .. 4p+3] = (vertex i, first, number of in-arcs, end) and its
+    // arcs are vinc[first .. end): in-arcs in ascending id, then out-arcs in
+    // ascending id (end - first = delta_i).
+    const int32_t *vinfo;    // 4n, 16-byte aligned
+    const int32_t *vinc;     // 2m
+    // 1: a pass's flows, heights and velocities fit in the Infinity Cache, so
+    // the sweep kernels use ordinary loads and stores and the data stays
+    // resident between passes; 0: they stream with non-temporal hints.
+    int32_t temporal;
 };
 
 struct AgdParams {

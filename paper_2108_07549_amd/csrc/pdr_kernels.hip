@@ -61,14 +61,11 @@ __device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&v)[VecT<T
 }
 
 // Streaming variants for data touched once per kernel (an arc's own flow
-// row): non-temporal accesses keep such rows from evicting the height rows
-// that neighbouring arcs re-read from L2.
-#ifndef PDR_ARC_NT
-#define PDR_ARC_NT 1
-#endif
-#ifndef PDR_HEIGHT_NT
-#define PDR_HEIGHT_NT 1
-#endif
+// row, a vertex's height row): non-temporal accesses keep such rows from
+// evicting the height rows that neighbouring arcs re-read from L2. When a
+// pass's whole working set fits in the Infinity Cache the sweep kernels use
+// the ordinary forms instead, so the data stays resident between passes
+// (DevGraph::temporal).
 typedef double pdr_d2 __attribute__((ext_vector_type(2)));
 typedef float pdr_f4 __attribute__((ext_vector_type(4)));
 
@@ -286,7 +283,7 @@ __global__ __launch_bounds__(1024) void kb_reduce(const InstView *__restrict__ v
 // report).
 // Work distribution: this block is block `blk` of `nblk` working on g; its
 // partials go to slot `part` (zpart[part], zpart[nblk + part], ...).
-template <typename T, bool RESID, int U>
+template <typename T, bool RESID, int U, bool NT = true>
 __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restrict__ f,
                                             T *__restrict__ h, double *__restrict__ h64,
                                             double *__restrict__ zpart,
@@ -316,46 +313,37 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
         const int64_t c = gid / per_chunk;
         const int64_t rem = gid - c * per_chunk;
         const int pos = (int)(rem / CV);
-        const int i = g.vorder[pos];
         const int q = (int)(c * CV + (rem - (int64_t)pos * CV));
         if (q >= nvec) continue;
+        // the vertex's record and its incidence list: in-arcs (+) then
+        // out-arcs (-), U rows loaded before they are summed (the summation
+        // order is the same for every U)
+        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 4 * (int64_t)pos);
+        const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
         const int k0 = q * V;
         double acc[V], mag[V];
 #pragma unroll
         for (int w = 0; w < V; ++w) acc[w] = mag[w] = 0.0;
-        // in-arcs (+) then out-arcs (-), U rows loaded before they are summed
-        // (the summation order is the same for every U)
-        const int p0 = g.in_ptr[i], p1 = g.in_ptr[i + 1];
         for (int p = p0; p < p1; p += U) {
+            int64_t e[U];
+#pragma unroll
+            for (int b = 0; b < U; ++b) e[b] = g.vinc[p + b < p1 ? p + b : p];
             T x[U][V];
 #pragma unroll
-            for (int b = 0; b < U; ++b) {
-                const int64_t e = g.in_idx[p + b < p1 ? p + b : p];
-                load_vec(f + e * Kp + k0, x[b]);
-            }
+            for (int b = 0; b < U; ++b) load_vec(f + e[b] * Kp + k0, x[b]);
 #pragma unroll
             for (int b = 0; b < U; ++b)
                 if (p + b < p1) {
+                    if (p + b < pin) {
 #pragma unroll
-                    for (int w = 0; w < V; ++w) {
-                        acc[w] += (double)x[b][w];
-                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
+                        for (int w = 0; w < V; ++w) acc[w] += (double)x[b][w];
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < V; ++w) acc[w] -= (double)x[b][w];
                     }
-                }
-        }
-        const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
-        for (int e = e0; e < e1; e += U) {
-            T x[U][V];
+                    if constexpr (kNoise) {
 #pragma unroll
-            for (int b = 0; b < U; ++b)
-                load_vec(f + (int64_t)(e + b < e1 ? e + b : e) * Kp + k0, x[b]);
-#pragma unroll
-            for (int b = 0; b < U; ++b)
-                if (e + b < e1) {
-#pragma unroll
-                    for (int w = 0; w < V; ++w) {
-                        acc[w] -= (double)x[b][w];
-                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
+                        for (int w = 0; w < V; ++w) mag[w] += fabs((double)x[b][w]);
                     }
                 }
         }
@@ -370,7 +358,7 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
                     if constexpr (kNoise) mag[w] += fabs(val);
                 }
         }
-        const int dg = g.deg[i];
+        const int dg = p1 - p0;
         T hv[V];
         double hd[V];
 #pragma unroll
@@ -391,7 +379,7 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
             for (int w = 0; w < V; w += 2)
                 *reinterpret_cast<double2 *>(dst + w) = make_double2(hd[w], hd[w + 1]);
         } else {
-            store_vec_s<PDR_HEIGHT_NT>(h + (int64_t)i * Kp + k0, hv);
+            store_vec_s<NT>(h + (int64_t)i * Kp + k0, hv);
         }
     }
     double ps = 0.0;
@@ -423,7 +411,7 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
     }
 }
 
-template <typename T, bool RESID, int U>
+template <typename T, bool RESID, int U, bool NT>
 __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
                                                 T *__restrict__ h, double *__restrict__ h64,
                                                 double *__restrict__ zpart,
@@ -432,8 +420,8 @@ __global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict_
                                                 const Ctrl *__restrict__ ctrl)
 {
     if (!RESID && ctrl->stopped) return;
-    height_core<T, RESID, U>(g, f, h, h64, zpart, maxpart, Fsum,
-                             xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
+    height_core<T, RESID, U, NT>(g, f, h, h64, zpart, maxpart, Fsum,
+                                 xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
 }
 
 // Batched: hmap[logical block] = (instance, block within the instance); the
@@ -472,7 +460,7 @@ struct ArcShape {
 // projection of c onto {f >= 0, sum f <= u}, with lambda = (sum_A c - u)/|A|
 // found by the same iteration; at u = 0 the set can empty (every c equal to
 // lambda), which also ends it.
-template <typename T, int L, int NV, bool CAP = false>
+template <typename T, int L, int NV, bool CAP = false, bool NT = true>
 __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, int64_t slot, int lane, double *lds)
 {
     constexpr int V = VecT<T>::N;
@@ -492,7 +480,7 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], b[V], x[V];
-            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
+            load_vec_s<NT>(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, b);
 #pragma unroll
@@ -549,14 +537,14 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
                 o[w] = (T)(val > 0.0 ? val : 0.0);
                 fs[0] += (double)o[w];
             }
-            store_vec_s<PDR_ARC_NT>(fo + q * V, o);
+            store_vec_s<NT>(fo + q * V, o);
         }
     }
     group_sum<L, 1>(fs, lds, phase);
     if (lane == 0) Fsum[e] = fs[0];
 }
 
-template <typename T, int L, int NV, bool CAP>
+template <typename T, int L, int NV, bool CAP, bool NT>
 __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restrict__ f,
                                                           const T *__restrict__ h,
                                                           double *__restrict__ Fsum,
@@ -570,7 +558,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    eso_arc<T, L, NV, CAP>(g, f, h, Fsum, slot, lane, lds);
+    eso_arc<T, L, NV, CAP, NT>(g, f, h, Fsum, slot, lane, lds);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
@@ -596,7 +584,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void kb_eso(const InstView *__rest
 // dz = 1/2[(F + sum df - u)_+^2 - psi^2] + sum_k df_k (df_k - (h_ik - h_jk)),
 // is <= 0; otherwise beta <- max(beta_min, alpha_dec beta). Every inc_period
 // iterations beta <- min(beta_max, alpha_inc beta).
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool NT = true>
 __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, double *__restrict__ beta, const AgdParams &prm, const Ctrl *__restrict__ ctrl, int64_t slot, int lane, double *lds)
 {
     constexpr int V = VecT<T>::N;
@@ -619,7 +607,7 @@ __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, co
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], bb[V], x[V];
-            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
+            load_vec_s<NT>(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, bb);
 #pragma unroll
@@ -654,7 +642,7 @@ __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, co
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int q = v * L + lane;
-            if (q < nvec) store_vec_s<PDR_ARC_NT>(fo + q * V, cand[v]);
+            if (q < nvec) store_vec_s<NT>(fo + q * V, cand[v]);
         }
     }
     if (lane == 0) {
@@ -667,7 +655,7 @@ __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, co
     }
 }
 
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool NT>
 __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restrict__ f,
                                                           const T *__restrict__ h,
                                                           double *__restrict__ Fsum,
@@ -683,7 +671,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    agd_arc<T, L, NV>(g, f, h, Fsum, beta, prm, ctrl, slot, lane, lds);
+    agd_arc<T, L, NV, NT>(g, f, h, Fsum, beta, prm, ctrl, slot, lane, lds);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
@@ -707,7 +695,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void kb_agd(const InstView *__rest
 // of Algorithm 3 (k_agd); an accepted arc takes v' = gamma v + df and
 // f' = max(0, f + v'), a rejected one keeps f and v and lowers beta. beta's
 // periodic increase is as in k_agd.
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool NT = true>
 __device__ __forceinline__ void gdm_arc(const DevGraph &g, T *__restrict__ f, T *__restrict__ vel, const T *__restrict__ h, double *__restrict__ Fsum, double *__restrict__ beta, const AgdParams &prm, const Ctrl *__restrict__ ctrl, int64_t slot, int lane, double *lds)
 {
     constexpr int V = VecT<T>::N;
@@ -732,8 +720,8 @@ __device__ __forceinline__ void gdm_arc(const DevGraph &g, T *__restrict__ f, T 
         const int q = v * L + lane;
         if (q < nvec) {
             T a[V], bb[V], x[V], w0[V];
-            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
-            load_vec_s<PDR_ARC_NT>(ve + q * V, w0);
+            load_vec_s<NT>(fe + q * V, x);
+            load_vec_s<NT>(ve + q * V, w0);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, bb);
 #pragma unroll
@@ -769,8 +757,8 @@ __device__ __forceinline__ void gdm_arc(const DevGraph &g, T *__restrict__ f, T 
         for (int v = 0; v < NV; ++v) {
             const int q = v * L + lane;
             if (q < nvec) {
-                store_vec_s<PDR_ARC_NT>(fo + q * V, nf[v]);
-                store_vec_s<PDR_ARC_NT>(vo + q * V, nv[v]);
+                store_vec_s<NT>(fo + q * V, nf[v]);
+                store_vec_s<NT>(vo + q * V, nv[v]);
             }
         }
     }
@@ -784,7 +772,7 @@ __device__ __forceinline__ void gdm_arc(const DevGraph &g, T *__restrict__ f, T 
     }
 }
 
-template <typename T, int L, int NV>
+template <typename T, int L, int NV, bool NT>
 __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restrict__ f,
                                                           T *__restrict__ vel,
                                                           const T *__restrict__ h,
@@ -801,7 +789,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_gdm(DevGraph g, T *__restri
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    gdm_arc<T, L, NV>(g, f, vel, h, Fsum, beta, prm, ctrl, slot, lane, lds);
+    gdm_arc<T, L, NV, NT>(g, f, vel, h, Fsum, beta, prm, ctrl, slot, lane, lds);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
@@ -845,7 +833,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
         const int q = v * L + lane;
         if (q < nvec) {
             T x[V];
-            load_vec_s<PDR_ARC_NT>(fe + q * V, x);
+            load_vec_s<true>(fe + q * V, x);
 #pragma unroll
             for (int w = 0; w < V; ++w) fs[0] += (double)x[w];
         }
@@ -1034,6 +1022,18 @@ hipError_t launch_begin(Ctrl *ctrl, double eps_obj, double z_target, hipStream_t
 
 #define PDR_HEIGHT_UNROLL(X) X(1) X(2) X(4) X(8)
 
+template <typename T, int U>
+static void height_launch(const DevGraph &g, const T *f, T *h, double *zpart, const double *Fsum,
+                          Ctrl *ctrl, unsigned nb, hipStream_t st)
+{
+    if (g.temporal)
+        k_height<T, false, U, false><<<nb, 256, 0, st>>>(g, f, h, nullptr, zpart, nullptr, Fsum,
+                                                         ctrl);
+    else
+        k_height<T, false, U, true><<<nb, 256, 0, st>>>(g, f, h, nullptr, zpart, nullptr, Fsum,
+                                                        ctrl);
+}
+
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
                          const double *Fsum, Ctrl *ctrl, double *zlog, int64_t zmask,
                          hipStream_t st)
@@ -1043,11 +1043,10 @@ hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, d
 #define PDR_H(U_)                                                                               \
     if (!launched && g.height_unroll == U_) {                                                   \
         if (fp64)                                                                               \
-            k_height<double, false, U_><<<nb, 256, 0, st>>>(g, (const double *)f, (double *)h,  \
-                                                            nullptr, zpart, nullptr, Fsum, ctrl); \
+            height_launch<double, U_>(g, (const double *)f, (double *)h, zpart, Fsum, ctrl, nb,  \
+                                      st);                                                      \
         else                                                                                    \
-            k_height<float, false, U_><<<nb, 256, 0, st>>>(g, (const float *)f, (float *)h,     \
-                                                           nullptr, zpart, nullptr, Fsum, ctrl); \
+            height_launch<float, U_>(g, (const float *)f, (float *)h, zpart, Fsum, ctrl, nb, st); \
         launched = true;                                                                        \
     }
     PDR_HEIGHT_UNROLL(PDR_H)
@@ -1064,10 +1063,10 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     if (fp64)
-        k_height<double, true, 4><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
+        k_height<double, true, 4, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
                                                       maxpart, nullptr, nullptr);
     else
-        k_height<float, true, 4><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart,
+        k_height<float, true, 4, true><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64, zpart,
                                                      maxpart, nullptr, nullptr);
     return hipGetLastError();
 }
@@ -1113,6 +1112,40 @@ static inline unsigned arc_blocks(int64_t m, int L)
     return (unsigned)((m + gpb - 1) / gpb);
 }
 
+// The single-context sweep kernels come in two cache-hint variants; the
+// graph's `temporal` flag picks one (DevGraph::temporal).
+template <typename T, int L, int NV>
+static void eso_launch(const DevGraph &g, T *f, const T *h, double *Fsum, const Ctrl *ctrl,
+                       bool cap, unsigned nb, hipStream_t st)
+{
+    constexpr int BS = ArcShape<L>::BS;
+    if (g.temporal) {
+        if (cap) k_eso<T, L, NV, true, false><<<nb, BS, 0, st>>>(g, f, h, Fsum, ctrl);
+        else k_eso<T, L, NV, false, false><<<nb, BS, 0, st>>>(g, f, h, Fsum, ctrl);
+    } else {
+        if (cap) k_eso<T, L, NV, true, true><<<nb, BS, 0, st>>>(g, f, h, Fsum, ctrl);
+        else k_eso<T, L, NV, false, true><<<nb, BS, 0, st>>>(g, f, h, Fsum, ctrl);
+    }
+}
+
+template <typename T, int L, int NV>
+static void agd_launch(const DevGraph &g, T *f, const T *h, double *Fsum, double *beta,
+                       const AgdParams &prm, const Ctrl *ctrl, T *vel, unsigned nb, hipStream_t st)
+{
+    constexpr int BS = ArcShape<L>::BS;
+    if (vel) {
+        if (g.temporal)
+            k_gdm<T, L, NV, false><<<nb, BS, 0, st>>>(g, f, vel, h, Fsum, beta, prm, ctrl);
+        else
+            k_gdm<T, L, NV, true><<<nb, BS, 0, st>>>(g, f, vel, h, Fsum, beta, prm, ctrl);
+    } else {
+        if (g.temporal)
+            k_agd<T, L, NV, false><<<nb, BS, 0, st>>>(g, f, h, Fsum, beta, prm, ctrl);
+        else
+            k_agd<T, L, NV, true><<<nb, BS, 0, st>>>(g, f, h, Fsum, beta, prm, ctrl);
+    }
+}
+
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
                       double *Fsum, const Ctrl *ctrl, bool cap, hipStream_t st)
 {
@@ -1120,19 +1153,11 @@ hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
 #define PDR_ESO_CASE(L_, NV_)                                                                    \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
         const unsigned nb = arc_blocks(g.m, L_);                                                 \
-        constexpr int BS = L_ > 64 ? L_ : 256;                                                   \
-        if (fp64 && !cap)                                                                        \
-            k_eso<double, L_, NV_, false><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h,  \
-                                                             Fsum, ctrl);                        \
-        else if (fp64)                                                                           \
-            k_eso<double, L_, NV_, true><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h,   \
-                                                            Fsum, ctrl);                         \
-        else if (!cap)                                                                           \
-            k_eso<float, L_, NV_, false><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h,     \
-                                                            Fsum, ctrl);                         \
+        if (fp64)                                                                                \
+            eso_launch<double, L_, NV_>(g, (double *)f, (const double *)h, Fsum, ctrl, cap, nb,   \
+                                        st);                                                     \
         else                                                                                     \
-            k_eso<float, L_, NV_, true><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h,      \
-                                                           Fsum, ctrl);                          \
+            eso_launch<float, L_, NV_>(g, (float *)f, (const float *)h, Fsum, ctrl, cap, nb, st); \
         return hipGetLastError();                                                                \
     }
     PDR_TILINGS(PDR_ESO_CASE)
@@ -1148,19 +1173,12 @@ hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
 #define PDR_AGD_CASE(L_, NV_)                                                                  \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
         const unsigned nb = arc_blocks(g.m, L_);                                               \
-        constexpr int BS = L_ > 64 ? L_ : 256;                                                 \
-        if (vel && fp64)                                                                       \
-            k_gdm<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (double *)vel,           \
-                                                      (const double *)h, Fsum, beta, prm, ctrl); \
-        else if (vel)                                                                          \
-            k_gdm<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (float *)vel,              \
-                                                     (const float *)h, Fsum, beta, prm, ctrl); \
-        else if (fp64)                                                                         \
-            k_agd<double, L_, NV_><<<nb, BS, 0, st>>>(g, (double *)f, (const double *)h, Fsum, \
-                                                      beta, prm, ctrl);                        \
+        if (fp64)                                                                              \
+            agd_launch<double, L_, NV_>(g, (double *)f, (const double *)h, Fsum, beta, prm, ctrl, \
+                                        (double *)vel, nb, st);                                \
         else                                                                                   \
-            k_agd<float, L_, NV_><<<nb, BS, 0, st>>>(g, (float *)f, (const float *)h, Fsum,    \
-                                                     beta, prm, ctrl);                         \
+            agd_launch<float, L_, NV_>(g, (float *)f, (const float *)h, Fsum, beta, prm, ctrl,  \
+                                       (float *)vel, nb, st);                                  \
         return hipGetLastError();                                                              \
     }
     PDR_TILINGS(PDR_AGD_CASE)

@@ -92,6 +92,8 @@ def test_init_rejects_isolated_commodity_endpoint():
     (dict(z_feasible_tol=-1.0), "z_feasible_tol"),
     (dict(lanes_per_arc=3), "tiling"),
     (dict(lanes_per_arc=1, vec_per_lane=1), "tiling"),  # K=100 needs more than 1 x 1 vectors
+    (dict(cache_policy=3), "cache_policy"),
+    (dict(cache_policy=-1), "cache_policy"),
 ])
 def test_init_rejects_invalid_options(opts, fragment):
     a = _good()

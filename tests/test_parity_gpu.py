@@ -129,6 +129,28 @@ def test_every_tiling_gives_the_same_iterates(method, precision):
             assert np.max(np.abs(f - ref)) <= flow_tol(inst)
 
 
+@pytest.mark.parametrize("precision", [pdr.FP64, pdr.FP32_BULK])
+@pytest.mark.parametrize("method", ALL)
+def test_cache_hints_do_not_change_the_iterates(method, precision):
+    """Ordinary (cache-resident) and non-temporal loads and stores run the same
+    passes bit for bit; the automatic choice keeps this small instance resident."""
+    gm, om = METHODS[method]
+    inst = recipe_small("knn", 30, 61, seed=8, u_range=(2, 9), d_range=(1, 6))
+    T = 40
+    runs = []
+    for pol in (0, 1, 2):
+        with ctx_for(inst, gm, precision, cache_policy=pol) as c:
+            c.sweep(T)
+            runs.append((c.flows(), c.z_log(0, T), c.learning_rates()))
+    for r in runs[1:]:
+        assert np.array_equal(r[0], runs[0][0])
+        assert np.array_equal(r[1], runs[0][1])
+        assert np.array_equal(r[2], runs[0][2])
+    if precision == pdr.FP64:
+        st, _ = oracle.run(inst, om, T)
+        assert np.max(np.abs(runs[0][0] - st.f)) <= flow_tol(inst)
+
+
 @pytest.mark.parametrize("K", [1, 2, 3, 5, 31, 33, 63, 65, 127, 129, 255, 257, 1000, 1025, 3001])
 @pytest.mark.parametrize("method", ALL)
 def test_ragged_commodity_counts(method, K):
