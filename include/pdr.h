@@ -327,9 +327,12 @@ pdr_status pdr_batch_stopped(pdr_batch *batch, int32_t *n_stopped);
  * covers the bucket's longest row (at most twice its size) with `reps`
  * launches of the batched arc kernel on the current heights, and give the
  * bucket's members the fastest; then time the batched height launch with
- * 8192, 16384, 32768 and 65536 blocks and keep the fastest (written to
- * *height_blocks unless NULL). The run state is saved before and restored
- * after (results are unchanged); buckets that end with the same tiling merge. */
+ * 8192, 16384, 32768 and 65536 blocks and pick the fastest. Finally `reps`
+ * whole passes are timed with these choices and with the starting ones, and
+ * the faster configuration stays (its height block count is written to
+ * *height_blocks unless NULL; each bucket's `ms` is its arc launch time under
+ * it). The run state is saved before and restored after (results are
+ * unchanged); buckets that end with the same tiling merge. */
 pdr_status pdr_batch_tune(pdr_batch *batch, int32_t reps, int64_t *height_blocks);
 
 /* The current tiling buckets: *n_buckets receives their number, out[0 ..

@@ -546,6 +546,10 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     const int V = fp64 ? 2 : 4;
     std::vector<int32_t> all(b->B);
     for (int32_t i = 0; i < b->B; ++i) all[i] = i;
+    // the starting configuration, kept if the tuned one is not faster
+    std::vector<Tiling> start_tl(b->B);
+    for (int32_t i = 0; i < b->B; ++i) start_tl[i] = b->members[i]->tiling;
+    const int64_t start_budget = b->height_budget;
     Snapshot sn;
     PDR_BCHECK(b, snapshot_members(b, sn, all, true));
     // heights of the current flows, so the arc kernels see the real workload
@@ -556,7 +560,6 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     PDR_BCHECK(b, hipEventCreate(&e0));
     PDR_BCHECK(b, hipEventCreate(&e1));
     std::vector<Tiling> best(b->buckets.size());
-    std::vector<double> best_ms(b->buckets.size(), 0.0);
     hipError_t err = hipSuccess;
     for (size_t q = 0; q < b->buckets.size() && err == hipSuccess; ++q) {
         const auto &bk = b->buckets[q];
@@ -597,14 +600,11 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
             }
         if (amap) (void)hipFree(amap);
         best[q] = bt;
-        best_ms[q] = bms;
     }
     // each member's chosen tiling (the bucket list is rebuilt below)
     std::vector<Tiling> member_tl(b->B);
     for (size_t q = 0; q < b->buckets.size(); ++q)
         for (int32_t i : b->buckets[q].members) member_tl[i] = best[q];
-    std::vector<std::pair<Tiling, double>> tuned_ms;
-    for (size_t q = 0; q < b->buckets.size(); ++q) tuned_ms.emplace_back(best[q], best_ms[q]);
     // the height launch: blocks in all (each member's share by work)
     int64_t best_budget = b->height_budget;
     double best_hms = std::numeric_limits<double>::infinity();
@@ -631,21 +631,75 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
             best_budget = cand;
         }
     }
-    b->height_budget = best_budget;
+    // The pieces were timed alone; a pass runs the buckets side by side after
+    // the height launch. Time whole passes (from the saved state, stop tests
+    // off) with the tuned and with the starting configuration and keep the
+    // faster.
+    auto apply = [&](const std::vector<Tiling> &tl, int64_t budget) -> pdr_status {
+        for (int32_t i = 0; i < b->B; ++i) b->members[i]->tiling = tl[i];
+        b->height_budget = budget;
+        return build_maps(b);
+    };
+    auto time_passes = [&](double *ms_out) -> hipError_t {
+        hipError_t e = snapshot_members(b, sn, all, false);
+        if (e == hipSuccess) e = pdr::launch_bbegin(b->d_views, b->B, 0.0, 0.0, b->stream);
+        if (e == hipSuccess) e = enqueue_batch_passes(b, 1, b->stream, b->aux);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = enqueue_batch_passes(b, reps, b->stream, b->aux);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        *ms_out = (double)ms / reps;
+        return e;
+    };
+    double t_tuned = 0.0, t_start = 0.0;
+    if (err == hipSuccess) {
+        st = apply(member_tl, best_budget);
+        if (st != PDR_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        err = time_passes(&t_tuned);
+    }
+    if (err == hipSuccess) {
+        st = apply(start_tl, start_budget);
+        if (st != PDR_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        err = time_passes(&t_start);
+    }
+    const bool keep_tuned = err == hipSuccess && t_tuned < t_start;
+    if (err == hipSuccess && keep_tuned) {
+        st = apply(member_tl, best_budget);
+        if (st != PDR_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+    }
+    // each final bucket's arc launch on the saved state, for pdr_batch_buckets
+    for (auto &bk : b->buckets) {
+        if (err != hipSuccess) break;
+        err = restore_members(b, sn, bk.members);
+        if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r)
+            err = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl,
+                                   b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        bk.ms = (double)ms / reps;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err == hipSuccess) err = snapshot_members(b, sn, all, false);
     PDR_BCHECK(b, err);
-    for (int32_t i = 0; i < b->B; ++i) b->members[i]->tiling = member_tl[i];
-    st = build_maps(b);
-    if (st != PDR_OK) return st;
     if (height_blocks) *height_blocks = b->height_budget;
-    // record the tuned time of each (possibly merged) bucket
-    for (auto &bk : b->buckets) {
-        bk.ms = 0.0;
-        for (const auto &x : tuned_ms)
-            if (x.first.lanes == bk.tl.lanes && x.first.nv == bk.tl.nv) bk.ms += x.second;
-    }
     return PDR_OK;
 }
 
