@@ -242,7 +242,9 @@ pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
  * (0 = 16) and each segment is recomputed once during the reverse sweep;
  * working memory of about (T/checkpoint + checkpoint) m K + (checkpoint + 1)
  * n K doubles is allocated for the call. Needs method PDR_ESO and precision PDR_FP64
- * (PDR_ERR_STATE otherwise). Synchronizes. */
+ * (PDR_ERR_STATE otherwise). If z(f^T) is not finite it returns
+ * PDR_ERR_NUMERIC (the context is then at f^T, as after pdr_sweep) and writes
+ * no gradient. Synchronizes. */
 pdr_status pdr_adjoint(pdr_ctx *ctx, int64_t T, int32_t checkpoint, double *z_out,
                        double *grad_u, double *grad_d);
 

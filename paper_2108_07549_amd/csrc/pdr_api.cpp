@@ -1153,7 +1153,7 @@ pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
     // the FP64 heights of f^T in h64)
     pdr_residual_t res;
     st = pdr_residual(c, &res);
-    if (st != PDR_OK && st != PDR_ERR_NUMERIC) return st;
+    if (st != PDR_OK) return st;  // PDR_ERR_NUMERIC: z(f^T) is not finite
     PDR_CHECK(c, pdr::launch_adj_seed(c->g, c->Fsum, c->h64, cbar, ubar, dbar, c->stream));
     PDR_CHECK(c, hipMemsetAsync(Dbar, 0, nK * 8, c->stream));
     // ---- reverse, segment by segment from the last: recompute the segment's
