@@ -626,18 +626,28 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     {
         // incidence lists in visiting order (in-arcs, then out-arcs, each in
         // ascending id: the summation order of the excess)
-        std::vector<int32_t> vinfo(4 * (size_t)n), vinc(2 * (size_t)m > 0 ? 2 * (size_t)m : 1);
+        std::vector<int32_t> vinfo(8 * (size_t)n), vinc(2 * (size_t)m > 0 ? 2 * (size_t)m : 1);
         int32_t p = 0;
         for (int32_t pos = 0; pos < n; ++pos) {
             const int32_t i = vorder[pos];
-            vinfo[4 * (size_t)pos] = i;
-            vinfo[4 * (size_t)pos + 1] = p;
-            vinfo[4 * (size_t)pos + 2] = in_ptr[i + 1] - in_ptr[i];
+            int32_t *vi = &vinfo[8 * (size_t)pos];
+            vi[0] = i;
+            vi[1] = p;
+            vi[2] = in_ptr[i + 1] - in_ptr[i];
             for (int32_t q = in_ptr[i]; q < in_ptr[i + 1]; ++q) vinc[p++] = in_idx[q];
             for (int32_t e = rp32[i]; e < rp32[i + 1]; ++e) vinc[p++] = e;
-            vinfo[4 * (size_t)pos + 3] = p;
+            vi[3] = p;
+            // injections: the kernel skips them for vectors outside [kmin, kmax]
+            vi[4] = inj_ptr[i];
+            vi[5] = inj_ptr[i + 1];
+            vi[6] = K;
+            vi[7] = -1;
+            for (int32_t q = inj_ptr[i]; q < inj_ptr[i + 1]; ++q) {
+                vi[6] = std::min(vi[6], inj_k[q]);
+                vi[7] = std::max(vi[7], inj_k[q]);
+            }
         }
-        PDR_UP(c->d_vinfo, vinfo.data(), 4 * (size_t)n);
+        PDR_UP(c->d_vinfo, vinfo.data(), 8 * (size_t)n);
         PDR_UP(c->d_vinc, vinc.data(), vinc.size());
     }
 #undef PDR_UP

@@ -48,10 +48,12 @@ struct DevGraph {
     const int32_t *vorder;   // n: order in which the height kernel visits vertices
     const int32_t *aorder;   // m: order in which the arc kernels visit arcs
     // Incidence lists in visiting order: position p of vorder has
-    // vinfo[4p .. 4p+3] = (vertex i, first, number of in-arcs, end) and its
+    // vinfo[8p .. 8p+3] = (vertex i, first, number of in-arcs, end) and its
     // arcs are vinc[first .. end): in-arcs in ascending id, then out-arcs in
-    // ascending id (end - first = delta_i).
-    const int32_t *vinfo;    // 4n, 16-byte aligned
+    // ascending id (end - first = delta_i); vinfo[8p+4 .. 8p+7] =
+    // (inj_ptr[i], inj_ptr[i+1], smallest and largest commodity injected at
+    // i; K and -1 if none).
+    const int32_t *vinfo;    // 8n, 16-byte aligned
     const int32_t *vinc;     // 2m
     // 1: a pass's flows, heights and velocities fit in the Infinity Cache, so
     // the sweep kernels use ordinary loads and stores and the data stays

@@ -318,45 +318,52 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
         // the vertex's record and its incidence list: in-arcs (+) then
         // out-arcs (-), U rows loaded before they are summed (the summation
         // order is the same for every U)
-        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 4 * (int64_t)pos);
+        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
+        // the injection record: loaded with the arc list in FP64 (its latency
+        // then overlaps the row loads), after the rows in FP32 (whose wider
+        // vectors leave no registers to hold it through the loop at 8 waves)
+        const int4 *vjp = reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
+        int4 vj = make_int4(0, 0, 0, -1);
+        if constexpr (sizeof(T) == 8) vj = *vjp;
         const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
         const int k0 = q * V;
         double acc[V], mag[V];
 #pragma unroll
         for (int w = 0; w < V; ++w) acc[w] = mag[w] = 0.0;
         for (int p = p0; p < p1; p += U) {
-            int64_t e[U];
+            int e[U];
 #pragma unroll
             for (int b = 0; b < U; ++b) e[b] = g.vinc[p + b < p1 ? p + b : p];
             T x[U][V];
 #pragma unroll
-            for (int b = 0; b < U; ++b) load_vec(f + e[b] * Kp + k0, x[b]);
+            for (int b = 0; b < U; ++b) load_vec(f + (int64_t)e[b] * Kp + k0, x[b]);
 #pragma unroll
             for (int b = 0; b < U; ++b)
                 if (p + b < p1) {
-                    if (p + b < pin) {
+                    // + for an in-arc, - for an out-arc (sg * x is exact, so
+                    // this is acc + x or acc - x rounded once)
+                    const double sg = p + b < pin ? 1.0 : -1.0;
 #pragma unroll
-                        for (int w = 0; w < V; ++w) acc[w] += (double)x[b][w];
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < V; ++w) acc[w] -= (double)x[b][w];
-                    }
-                    if constexpr (kNoise) {
-#pragma unroll
-                        for (int w = 0; w < V; ++w) mag[w] += fabs((double)x[b][w]);
+                    for (int w = 0; w < V; ++w) {
+                        acc[w] += sg * (double)x[b][w];
+                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
                     }
                 }
         }
-        const int j0 = g.inj_ptr[i], j1 = g.inj_ptr[i + 1];
-        for (int p = j0; p < j1; ++p) {
-            const int k = g.inj_k[p] - k0;
-            const double val = g.inj_val[p];
+        // injections (hatDelta) of this vertex that fall in the vector's
+        // commodities [k0, k0 + V)
+        if constexpr (sizeof(T) == 4) vj = *vjp;
+        if (k0 <= vj.w && k0 + V > vj.z) {
+            for (int p = vj.x; p < vj.y; ++p) {
+                const int k = g.inj_k[p] - k0;
+                const double val = g.inj_val[p];
 #pragma unroll
-            for (int w = 0; w < V; ++w)
-                if (w == k) {
-                    acc[w] += val;
-                    if constexpr (kNoise) mag[w] += fabs(val);
-                }
+                for (int w = 0; w < V; ++w)
+                    if (w == k) {
+                        acc[w] += val;
+                        if constexpr (kNoise) mag[w] += fabs(val);
+                    }
+            }
         }
         const int dg = p1 - p0;
         T hv[V];
@@ -411,8 +418,11 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
     }
 }
 
+// Eight waves per SIMD (at most 64 VGPRs) for the unrolls up to 4, so that the
+// default grid (8 blocks of 4 waves on each of the 256 CUs) is resident at
+// once and no block starts late.
 template <typename T, bool RESID, int U, bool NT>
-__global__ __launch_bounds__(256) void k_height(DevGraph g, const T *__restrict__ f,
+__global__ __launch_bounds__(256, (U <= 4 ? 8 : 1)) void k_height(DevGraph g, const T *__restrict__ f,
                                                 T *__restrict__ h, double *__restrict__ h64,
                                                 double *__restrict__ zpart,
                                                 double *__restrict__ maxpart,
