@@ -319,17 +319,20 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
         // out-arcs (-), U rows loaded before they are summed (the summation
         // order is the same for every U)
         const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
-        // the injection record: loaded with the arc list in FP64 (its latency
-        // then overlaps the row loads), after the rows in FP32 (whose wider
-        // vectors leave no registers to hold it through the loop at 8 waves)
-        const int4 *vjp = reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
-        int4 vj = make_int4(0, 0, 0, -1);
-        if constexpr (sizeof(T) == 8) vj = *vjp;
+        // the injection record, loaded with the arc list so its latency
+        // overlaps the row loads
+        const int4 vj = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
         const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
         const int k0 = q * V;
-        double acc[V], mag[V];
+        // mag: the magnitude sum behind the FP32 noise estimate (an estimate,
+        // so single precision; it keeps the FP32 kernels within 64 VGPRs)
+        double acc[V];
+        float mag[V];
 #pragma unroll
-        for (int w = 0; w < V; ++w) acc[w] = mag[w] = 0.0;
+        for (int w = 0; w < V; ++w) {
+            acc[w] = 0.0;
+            mag[w] = 0.0f;
+        }
         for (int p = p0; p < p1; p += U) {
             int e[U];
 #pragma unroll
@@ -346,13 +349,12 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
 #pragma unroll
                     for (int w = 0; w < V; ++w) {
                         acc[w] += sg * (double)x[b][w];
-                        if constexpr (kNoise) mag[w] += fabs((double)x[b][w]);
+                        if constexpr (kNoise) mag[w] += fabsf((float)x[b][w]);
                     }
                 }
         }
         // injections (hatDelta) of this vertex that fall in the vector's
         // commodities [k0, k0 + V)
-        if constexpr (sizeof(T) == 4) vj = *vjp;
         if (k0 <= vj.w && k0 + V > vj.z) {
             for (int p = vj.x; p < vj.y; ++p) {
                 const int k = g.inj_k[p] - k0;
@@ -361,7 +363,7 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
                 for (int w = 0; w < V; ++w)
                     if (w == k) {
                         acc[w] += val;
-                        if constexpr (kNoise) mag[w] += fabs(val);
+                        if constexpr (kNoise) mag[w] += (float)fabs(val);
                     }
             }
         }
@@ -376,7 +378,7 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
             zs += acc[w] * hh;
             if (RESID) mx = fmax(mx, fabs(acc[w]));
             if constexpr (kNoise) {
-                const double r = kFp32Unit * mag[w];
+                const double r = kFp32Unit * (double)mag[w];
                 if (dg > 0) ns += r * r / (double)dg;
             }
         }
