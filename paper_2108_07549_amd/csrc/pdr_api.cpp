@@ -1176,9 +1176,8 @@ pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
                                                   c->maxpart, c->stream));
             if (k + 1 < b - a) {
                 double *nxt = seg[(size_t)k];
-                PDR_CHECK(c, hipMemcpyAsync(nxt, prev, mK * 8, hipMemcpyDeviceToDevice, c->stream));
-                PDR_CHECK(c, pdr::launch_eso(c->g, true, c->tiling, nxt, hseg[(size_t)k], c->Fsum,
-                                             c->ctrl, false, c->stream));
+                PDR_CHECK(c, pdr::launch_eso_oop(c->g, c->tiling, prev, nxt, hseg[(size_t)k],
+                                                 c->Fsum, c->stream));
                 prev = nxt;
             }
         }

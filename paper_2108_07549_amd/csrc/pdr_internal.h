@@ -105,6 +105,10 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
 // ESO arc update (Expression 14); cap: the capacity-enforcing step instead.
 hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,
                       double *Fsum, const Ctrl *ctrl, bool cap, hipStream_t st);
+// One FP64 ESO pass reading fin and writing fout (distinct buffers), no stop
+// test (the adjoint's segment recomputation).
+hipError_t launch_eso_oop(const DevGraph &g, Tiling tl, const double *fin, double *fout,
+                          const double *h, double *Fsum, hipStream_t st);
 // AGD arc update (Algorithm 3); with a velocity buffer vel, the GDM update
 // (Algorithm 4).
 hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const void *h,

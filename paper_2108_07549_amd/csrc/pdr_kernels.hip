@@ -472,15 +472,17 @@ struct ArcShape {
 // projection of c onto {f >= 0, sum f <= u}, with lambda = (sum_A c - u)/|A|
 // found by the same iteration; at u = 0 the set can empty (every c equal to
 // lambda), which also ends it.
+// fin: the flows to read when they differ from the flows written (f), as in
+// the adjoint's recomputation of a segment; nullptr updates f in place.
 template <typename T, int L, int NV, bool CAP = false, bool NT = true>
-__device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, int64_t slot, int lane, double *lds)
+__device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, int64_t slot, int lane, double *lds, const T *__restrict__ fin = nullptr)
 {
     constexpr int V = VecT<T>::N;
     int phase = 0;
     const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
-    const T *fe = f + e * Kp;
+    const T *fe = (fin ? fin : f) + e * Kp;
     const T *hi = h + (int64_t)g.tails[e] * Kp;
     const T *hj = h + (int64_t)g.heads[e] * Kp;
     const double u = g.u[e];
@@ -571,6 +573,25 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso(DevGraph g, T *__restri
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
     eso_arc<T, L, NV, CAP, NT>(g, f, h, Fsum, slot, lane, lds);
+}
+
+// One FP64 PDR-ESO pass out of place: reads fin, writes fout (the adjoint
+// recomputes a segment's flows from a checkpoint without copying it first).
+template <int L, int NV>
+__global__ __launch_bounds__(ArcShape<L>::BS) void k_eso_oop(DevGraph g,
+                                                              const double *__restrict__ fin,
+                                                              double *__restrict__ fout,
+                                                              const double *__restrict__ h,
+                                                              double *__restrict__ Fsum)
+{
+    using S = ArcShape<L>;
+    __shared__ double lds[2 * kRedMax * S::NW];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = (L >= S::BS) ? 0 : (int)threadIdx.x / L;
+    const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
+    const int64_t slot = blk * S::GPB + grp;
+    if (L <= 64 && slot >= g.m) return;
+    eso_arc<double, L, NV, false, true>(g, fout, h, Fsum, slot, lane, lds, fin);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
@@ -1174,6 +1195,21 @@ hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
     }
     PDR_TILINGS(PDR_ESO_CASE)
 #undef PDR_ESO_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_eso_oop(const DevGraph &g, Tiling tl, const double *fin, double *fout,
+                          const double *h, double *Fsum, hipStream_t st)
+{
+    if (g.m == 0) return hipSuccess;
+#define PDR_OOP_CASE(L_, NV_)                                                                   \
+    if (tl.lanes == L_ && tl.nv == NV_) {                                                       \
+        k_eso_oop<L_, NV_><<<arc_blocks(g.m, L_), ArcShape<L_>::BS, 0, st>>>(g, fin, fout, h,   \
+                                                                              Fsum);            \
+        return hipGetLastError();                                                               \
+    }
+    PDR_TILINGS(PDR_OOP_CASE)
+#undef PDR_OOP_CASE
     return hipErrorInvalidValue;
 }
 
