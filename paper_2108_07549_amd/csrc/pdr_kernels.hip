@@ -1400,10 +1400,10 @@ __device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__r
         const int q = v * L + lane;
         if (q < nvec) {
             double a[V], b[V], x[V], dh[V], dt[V];
-            load_vec(fe + q * V, x);
+            load_vec_s<true>(fe + q * V, x);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, b);
-            load_vec(ge + q * V, gg[v]);
+            load_vec_s<true>(ge + q * V, gg[v]);
             load_vec(Dh + q * V, dh);
             load_vec(Dt + q * V, dt);
 #pragma unroll
@@ -1469,7 +1469,7 @@ __device__ __forceinline__ void eso_bwd_arc(const DevGraph &g, const double *__r
             double o[V];
 #pragma unroll
             for (int w = 0; w < V; ++w) o[w] = c[v][w] - half > 0.0 ? gg[v][w] - share : 0.0;
-            store_vec(co + q * V, o);
+            store_vec_s<true>(co + q * V, o);
         }
     }
     if (congested && lane == 0) ubar[e] += share;
