@@ -156,6 +156,9 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
  * otherwise updates every arc (Jacobi: all arcs read the same h).
  * The stop test runs on the device. With no stop test active the call only
  * enqueues work; otherwise it polls the device between batches of passes.
+ * A non-finite objective stops the passes like a met stop test (before the
+ * update of that pass); pdr_residual, pdr_solve and pdr_adjoint then report
+ * PDR_ERR_NUMERIC.
  * Errors: PDR_ERR_INVALID for max_sweeps < 0; PDR_ERR_DEVICE.
  */
 pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_target);

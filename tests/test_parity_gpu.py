@@ -219,6 +219,28 @@ def test_two_vertex_infeasible_closed_form():
 
 
 @pytest.mark.parametrize("method", ALL)
+def test_non_finite_objective_stops_and_is_reported(method):
+    """Demands of 1e200 make z(0) = 1/2 d^2 (1/delta_s + 1/delta_t) overflow:
+    the device stops before the first update and the reads report it."""
+    gm, _ = METHODS[method]
+    inst = make_instance(3, [(0, 1), (1, 2), (2, 0)], 1.0, [0], [2], [1e200])
+    with ctx_for(inst, gm) as c:
+        c.sweep(10)
+        res = c.residual()
+        assert res["status"] == "PDR_ERR_NUMERIC"
+        assert res["sweeps_done"] == 0 and res["stopped"] == 1
+        assert np.all(c.flows() == 0.0)
+        with pytest.raises(pdr.PdrError) as ei:
+            c.solve(1e-8, 100)
+        assert ei.value.status == 5
+    if gm == pdr.ESO:
+        with ctx_for(inst, gm) as c:
+            with pytest.raises(pdr.PdrError) as ei:
+                c.adjoint(4, 2)
+            assert ei.value.status == 5
+
+
+@pytest.mark.parametrize("method", ALL)
 def test_degenerate_instances(method):
     gm, om = METHODS[method]
     cases = {
