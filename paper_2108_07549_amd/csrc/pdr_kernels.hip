@@ -1499,31 +1499,46 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_eso_bwd(DevGraph g,
 __global__ __launch_bounds__(256) void k_adj_vertex(DevGraph g, const double *__restrict__ cbar,
                                                     double *__restrict__ Dbar)
 {
+    // the height kernel's traversal (commodity-chunk-major items, vertices in
+    // locality order, each vertex's incidence list in U = 4 row batches),
+    // accumulating sum_in - sum_out of cbar; Dbar = -(that) / (2 delta)
+    constexpr int U = 4;
     const int nvec = g.Kp / 2;
-    const int64_t items = (int64_t)g.n * nvec;
-    for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
-         it += (int64_t)gridDim.x * 256) {
-        const int pos = (int)(it / nvec);  // vertices in the locality order
-        const int q = (int)(it - (int64_t)pos * nvec);
-        const int i = g.vorder[pos];
+    const int64_t Kp = g.Kp;
+    const int CV = g.height_cv;
+    const int64_t per_chunk = (int64_t)g.n * CV;
+    const int64_t total = per_chunk * ((nvec + CV - 1) / CV);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    for (int64_t gid = blk * 256 + threadIdx.x; gid < total; gid += (int64_t)gridDim.x * 256) {
+        const int64_t c = gid / per_chunk;
+        const int64_t rem = gid - c * per_chunk;
+        const int pos = (int)(rem / CV);
+        const int q = (int)(c * CV + (rem - (int64_t)pos * CV));
+        if (q >= nvec) continue;
+        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
+        const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
+        const int k0 = 2 * q;
         double acc[2] = {0.0, 0.0};
-        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
-            double x[2];
-            load_vec(cbar + (int64_t)e * g.Kp + 2 * q, x);
-            acc[0] += x[0];
-            acc[1] += x[1];
+        for (int p = p0; p < p1; p += U) {
+            int e[U];
+#pragma unroll
+            for (int b = 0; b < U; ++b) e[b] = g.vinc[p + b < p1 ? p + b : p];
+            double x[U][2];
+#pragma unroll
+            for (int b = 0; b < U; ++b) load_vec(cbar + (int64_t)e[b] * Kp + k0, x[b]);
+#pragma unroll
+            for (int b = 0; b < U; ++b)
+                if (p + b < p1) {
+                    const double sg = p + b < pin ? 1.0 : -1.0;
+                    acc[0] += sg * x[b][0];
+                    acc[1] += sg * x[b][1];
+                }
         }
-        for (int p = g.in_ptr[i]; p < g.in_ptr[i + 1]; ++p) {
-            double x[2];
-            load_vec(cbar + (int64_t)g.in_idx[p] * g.Kp + 2 * q, x);
-            acc[0] -= x[0];
-            acc[1] -= x[1];
-        }
-        const int dg = g.deg[i];
+        const int dg = p1 - p0;
         double o[2];
-        o[0] = dg > 0 ? acc[0] / (2.0 * dg) : 0.0;
-        o[1] = dg > 0 ? acc[1] / (2.0 * dg) : 0.0;
-        store_vec(Dbar + (int64_t)i * g.Kp + 2 * q, o);
+        o[0] = dg > 0 ? -acc[0] / (2.0 * dg) : 0.0;
+        o[1] = dg > 0 ? -acc[1] / (2.0 * dg) : 0.0;
+        store_vec(Dbar + (int64_t)i * Kp + k0, o);
     }
 }
 
@@ -1557,7 +1572,7 @@ hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_adj_vertex<<<grid_for((int64_t)g.n * (g.Kp / 2), 16384), 256, 0, st>>>(g, cbar, Dbar);
+    k_adj_vertex<<<(unsigned)height_blocks(g, 8), 256, 0, st>>>(g, cbar, Dbar);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_adj_dbar<<<(g.K + 255) / 256, 256, 0, st>>>(g, Dbar, dbar, 1);
