@@ -427,6 +427,33 @@ def test_grid100_k10000_3_sweeps(method):
     assert np.allclose(r["zg"], r["zo"], rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("method,precision", [("eso", pdr.FP64), ("eso", pdr.FP32_BULK),
+                                              ("agd", pdr.FP64), ("gdm", pdr.FP64),
+                                              ("cap", pdr.FP64)])
+def test_scale_covariance_at_full_size(method, precision):
+    """Every step of a pass is positively homogeneous, so scaling u and d by 4
+    scales the iterates by 4 and z by 16, bit for bit (powers of two round
+    exactly): a check of the benchmark workload at full size that needs no
+    oracle. The learning rates do not change."""
+    try:
+        inst = load_instance("grid100_k10000")
+    except MissingLoadFactor as exc:
+        pytest.skip(f"load factor not certified yet: {exc}")
+    import dataclasses
+    gm, _ = METHODS[method]
+    big = dataclasses.replace(inst, u=inst.u * 4.0, d=inst.d * 4.0)
+    T = 3
+    out = []
+    for i2 in (inst, big):
+        with ctx_for(i2, gm, precision) as c:
+            c.sweep(T)
+            out.append((c.flows(), c.z_log(0, T), c.learning_rates()))
+    say("scale covariance", method, precision, float(np.max(out[0][0])))
+    assert np.array_equal(out[1][0], 4.0 * out[0][0])
+    assert np.array_equal(out[1][1], 16.0 * out[0][1])
+    assert np.array_equal(out[1][2], out[0][2])
+
+
 # ------------------------------------------------------------------ graph replays, solve
 @pytest.mark.parametrize("method", ALL)
 def test_graph_replays_match_direct_launches(method):
