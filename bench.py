@@ -216,10 +216,10 @@ def main():
                     help="skip the adjoint (reverse-mode gradient) timing")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
-    ap.add_argument("--ttr-workload", default="",
-                    help="also run FP64 and FP32 bulk + FP64 polish to z <= 1e-8 on this "
-                         "workload (e.g. knn2500_k1000; about a minute per method)")
-    ap.add_argument("--ttr-methods", default="eso,gdm",
+    ap.add_argument("--ttr-workload", default="knn2500_k1000",
+                    help="run FP64 and FP32 bulk + FP64 polish to z <= 1e-8 on this workload "
+                         "(about 75 s for ESO); 'none' skips it")
+    ap.add_argument("--ttr-methods", default="eso",
                     help="methods of --ttr-workload (eso, agd, gdm, cap)")
     ap.add_argument("--ttr-cap", type=int, default=2_000_000,
                     help="pass limit of each --ttr-workload run")
@@ -297,7 +297,7 @@ def main():
             ttr[name] = r
         out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
                                        target=1e-8, **ttr)
-    if args.ttr_workload:
+    if args.ttr_workload and args.ttr_workload != "none":
         tinst = load_instance(args.ttr_workload)
         full = dict(workload=args.ttr_workload, target=1e-8, cap=args.ttr_cap)
         names = {"eso": pdr.ESO, "agd": pdr.AGD, "gdm": pdr.GDM, "cap": pdr.CAP}
