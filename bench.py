@@ -218,8 +218,8 @@ def main():
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
     ap.add_argument("--ttr-workload", default="knn2500_k1000",
                     help="run FP64 and FP32 bulk + FP64 polish to z <= 1e-8 on this workload "
-                         "(about 75 s for ESO); 'none' skips it")
-    ap.add_argument("--ttr-methods", default="eso",
+                         "(about two minutes for ESO and GDM); 'none' skips it")
+    ap.add_argument("--ttr-methods", default="eso,gdm",
                     help="methods of --ttr-workload (eso, agd, gdm, cap)")
     ap.add_argument("--ttr-cap", type=int, default=2_000_000,
                     help="pass limit of each --ttr-workload run")

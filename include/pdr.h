@@ -172,9 +172,11 @@ pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_
  * adds rounding noise of size z_noise (the objective that rounding each stored
  * flow alone leaves, computed by the height kernel), and a descent that
  * shrinks z by (1 - rate) per pass settles near z_noise / rate (rate measured
- * over the last window). When z <= floor_factor * z_noise / rate (floor_factor
- * <= 0 means 5), or when z stalls (the smallest z of the window is not below
- * (1 - 1e-3) times the smallest before it), the flows are widened to FP64
+ * on the windows' smallest z over the last four windows). When the window's
+ * smallest z is <= floor_factor * z_noise / rate (floor_factor <= 0 means 5,
+ * or 0.03 for PDR_GDM, whose FP32 descent goes on far below the estimate),
+ * or when z stalls (four windows in a row whose smallest z is not below
+ * (1 - 1e-3) times the smallest before), the flows are widened to FP64
  * exactly (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
  * sweeps_fp32 / sweeps_fp64 (may be NULL) receive the passes run in each
  * precision. Errors: PDR_ERR_INVALID for z_target <= 0, max_sweeps < 0 or

@@ -747,9 +747,14 @@ pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t wi
     if (!usable(c, &st)) return st;
     if (!(z_target > 0.0) || max_sweeps < 0 || window < 1 || std::isnan(floor_factor))
         return fail(c, PDR_ERR_INVALID, "need z_target > 0, max_sweeps >= 0, window >= 1");
-    const double kappa = floor_factor > 0.0 ? floor_factor : kFloorFactor;
+    const double kappa = floor_factor > 0.0 ? floor_factor
+                         : c->method == PDR_GDM ? kFloorFactorGdm : kFloorFactor;
     int64_t n32 = 0, n64 = 0, total = 0;
     double best_before = std::numeric_limits<double>::infinity();
+    int stalled = 0;  // consecutive windows without a new lowest z
+    // lowest z and passes of the recent FP32 windows (the descent rate is
+    // measured over kRateWindows of them)
+    std::vector<std::pair<double, int64_t>> recent;
     std::vector<double> zl;
     while (total < max_sweeps) {
         st = sync_ctrl(c);
@@ -772,16 +777,24 @@ pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t wi
             const double cur = *std::min_element(zl.begin(), zl.end());
             // FP32 rounding adds noise of size z_noise every pass; a descent that
             // shrinks z by the factor (1 - rate) per pass settles where the two
-            // balance, near z_noise / rate. Hand over well before that level,
-            // or when the objective stalls.
-            const double z_first = zl.front(), z_last = zl.back();
-            const double rate = (z_first > 0.0 && z_last > 0.0 && z_last < z_first)
-                                    ? std::log(z_first / z_last) / (double)(nev - 1)
-                                    : 0.0;
-            const double floor_est =
-                rate > 0.0 ? c->h_ctrl->z_noise / rate : std::numeric_limits<double>::infinity();
-            const bool near_floor = z_last <= kappa * floor_est;
-            if (near_floor || !(cur < (1.0 - 1e-3) * best_before)) {
+            // balance, near z_noise / rate. Hand over at kappa times that
+            // level, or when the objective stalls. The rate is that of the
+            // windows' lowest z over the last kRateWindows windows: GDM's z is
+            // not monotone, so the ends of one window say little.
+            recent.emplace_back(cur, ran);
+            if ((int)recent.size() > kRateWindows + 1) recent.erase(recent.begin());
+            double rate = 0.0;
+            if ((int)recent.size() == kRateWindows + 1 && cur > 0.0 && cur < recent.front().first) {
+                int64_t span = 0;
+                for (size_t q = 1; q < recent.size(); ++q) span += recent[q].second;
+                rate = std::log(recent.front().first / cur) / (double)std::max<int64_t>(span, 1);
+            }
+            const bool near_floor = rate > 0.0 && cur <= kappa * (c->h_ctrl->z_noise / rate);
+            // a stall is kStallWindows windows in a row without a new lowest z
+            // (GDM's objective is not monotone: one window can miss the last
+            // trough and still be on the way down)
+            stalled = cur < (1.0 - 1e-3) * best_before ? 0 : stalled + 1;
+            if (near_floor || stalled >= kStallWindows) {
                 st = pdr_set_precision(c, PDR_FP64);
                 if (st != PDR_OK) return st;
             }

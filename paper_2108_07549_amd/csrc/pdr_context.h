@@ -25,9 +25,16 @@ constexpr int kHeightGridAuto = 2048;
 constexpr int kHeightUnrollAuto = 4;
 // Vertices per locality cluster of the visiting order.
 constexpr int kClusterAuto = 64;
-// FP32 bulk hands over to the FP64 polish once z is within this factor of the
-// estimated FP32 floor z_noise / rate (see pdr_solve).
+// pdr_solve hands FP32 bulk over to the FP64 polish once z is within
+// kFloorFactor of the estimated FP32 floor z_noise / rate, the descent rate
+// measured over kRateWindows windows (kFloorFactorGdm for GDM, whose FP32
+// descent keeps its FP64 pace far below that estimate: measured on a
+// 2,500-vertex k-NN instance with 1,000 commodities), or after kStallWindows
+// windows without a new lowest z.
 constexpr double kFloorFactor = 5.0;
+constexpr double kFloorFactorGdm = 0.03;
+constexpr int kRateWindows = 4;
+constexpr int kStallWindows = 4;
 // Flows + heights (+ velocities) of one pass at or below this size are kept
 // cache-resident (the MI355X Infinity Cache holds 256 MB).
 constexpr double kCacheResidentBytes = 256.0 * 1024.0 * 1024.0;
