@@ -292,7 +292,7 @@ def main():
         ttr = {}
         for name, prec in (("fp64", pdr.FP64), ("fp32_polish", pdr.FP32_BULK)):
             r = time_to_residual(pdr, inst, pdr.ESO, prec, args.ttr_budget,
-                                 [1e5, 1e4, 1e3, 1e2, 1e-8])
+                                 [1e5, 1e4, 1e3, 1e2, 1e1, 1.0, 1e-8])
             print(f"[bench] ttr eso {name}: {r}", file=sys.stderr, flush=True)
             ttr[name] = r
         out["time_to_residual"] = dict(method="eso", budget_s_per_variant=args.ttr_budget,
