@@ -74,10 +74,11 @@ def time_variant(pdr, inst, method, precision, steps, warmup):
                                               Kp=tiling[2]))
 
 
-def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=200):
+def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=2048, window=256):
     """Run from f = 0 for about budget_s seconds (FP32-bulk runs hand over to the
-    FP64 polish by pdr_solve's rule); return the wall time and sweep count at
-    which z first fell to each rung, and the final state."""
+    FP64 polish by pdr_solve's rule, judged on the windows inside each chunk);
+    return the wall time and sweep count at which z first fell to each rung,
+    and the final state."""
     out = {str(r): None for r in rungs}
     with pdr.Context.from_instance(inst, method=method, precision=precision) as ctx:
         pdr.device_synchronize()
@@ -85,7 +86,7 @@ def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=200):
         n32 = n64 = 0
         evals = 0
         while True:
-            a, b = ctx.solve(min(rungs), chunk, chunk)
+            a, b = ctx.solve(min(rungs), chunk, window)
             n32 += a
             n64 += b
             now = time.perf_counter() - t0
