@@ -178,6 +178,7 @@ pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_
  * or when z stalls (four windows in a row whose smallest z is not below
  * (1 - 1e-3) times the smallest before), the flows are widened to FP64
  * exactly (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
+ * The rate and stall tracking covers the windows of one call.
  * sweeps_fp32 / sweeps_fp64 (may be NULL) receive the passes run in each
  * precision. Errors: PDR_ERR_INVALID for z_target <= 0, max_sweeps < 0 or
  * window < 1; PDR_ERR_NUMERIC for a non-finite objective; PDR_ERR_DEVICE.
