@@ -190,21 +190,25 @@ def test_batch_rejects_a_bad_instance():
     assert ei.value.status == 1 and "instance 1" in ei.value.message
 
 
-def test_full_batch_sampled_members_match_the_oracle():
-    """The 256-instance batch the benchmark times (after tuning, FP64 ESO):
-    the largest, smallest and median members after 3 sweeps against the oracle."""
+@pytest.mark.parametrize("method", list(METHODS))
+def test_full_batch_sampled_members_match_the_oracle(method):
+    """The 256-instance batch the benchmark times (FP64; tuned for ESO, the
+    benchmark's method): the largest, smallest and median members after 3
+    sweeps against the oracle."""
     from gen.batch import recipe_batch
+    gm, om = METHODS[method]
     insts = recipe_batch(256, 4)
     work = np.array([i.m * i.K for i in insts])
     order = np.argsort(work)
     picks = [int(order[-1]), int(order[0]), int(order[len(order) // 2])]
-    with pdr.Batch(insts, method=pdr.ESO, precision=pdr.FP64) as b:
-        say("full batch buckets", b.tune(reps=2))
+    with pdr.Batch(insts, method=gm, precision=pdr.FP64) as b:
+        if method == "eso":
+            say("full batch buckets", b.tune(reps=2))
         b.sweep(3)
         for q in picks:
             inst = insts[q]
-            say("full batch member", q, inst.n, inst.m, inst.K)
-            st, zo = oracle.run(inst, oracle.ESO, 3)
+            say("full batch member", method, q, inst.n, inst.m, inst.K)
+            st, zo = oracle.run(inst, om, 3)
             c = b.member(q)
             assert np.max(np.abs(c.flows() - st.f)) <= flow_tol(inst), q
             assert np.allclose(c.z_log(0, 3), zo, rtol=1e-11, atol=0), q
