@@ -72,7 +72,8 @@ def test_ragged_commodities_and_tilings():
 
 def test_adjoint_needs_fp64_eso():
     inst = recipe_grid4_k8()
-    for kw in (dict(method=pdr.AGD), dict(method=pdr.ESO, precision=pdr.FP32_BULK)):
+    for kw in (dict(method=pdr.AGD), dict(method=pdr.GDM), dict(method=pdr.CAP),
+               dict(method=pdr.ESO, precision=pdr.FP32_BULK)):
         with pdr.Context.from_instance(inst, **kw) as c:
             with pytest.raises(pdr.PdrError) as ei:
                 c.adjoint(4)
