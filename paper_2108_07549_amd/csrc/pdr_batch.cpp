@@ -343,8 +343,10 @@ hipError_t snap_copy(Snapshot &sn, size_t slot, void *dst_or_src, size_t bytes, 
     return hipMemcpyAsync(dst_or_src, sn.bufs[slot], bytes, hipMemcpyDeviceToDevice, st);
 }
 
-// Buffers saved per member: f, Fsum, beta, the control record and (GDM) v.
-size_t slots_per_member(const pdr_batch *b) { return b->method == PDR_GDM ? 5 : 4; }
+// Buffers saved per member: f, Fsum, beta, the control record, the z log (the
+// tuner's whole passes write entries that, once the ring has wrapped, hold
+// retained evaluations) and (GDM) v.
+size_t slots_per_member(const pdr_batch *b) { return b->method == PDR_GDM ? 6 : 5; }
 
 // Save (save = true) or restore the state of the listed members; a snapshot
 // of every member in index order (the tuner's) keeps member i's buffers at
@@ -360,6 +362,8 @@ hipError_t snapshot_members(pdr_batch *b, Snapshot &sn, const std::vector<int32_
         if (e == hipSuccess) e = snap_copy(sn, slot++, c->Fsum, (size_t)c->m * 8, save, b->stream);
         if (e == hipSuccess) e = snap_copy(sn, slot++, c->beta, (size_t)c->m * 8, save, b->stream);
         if (e == hipSuccess) e = snap_copy(sn, slot++, c->ctrl, sizeof(Ctrl), save, b->stream);
+        if (e == hipSuccess)
+            e = snap_copy(sn, slot++, c->zlog, (size_t)c->zlog_cap * 8, save, b->stream);
         if (e == hipSuccess && c->method == PDR_GDM)
             e = snap_copy(sn, slot++, cur_v(c), mK * w, save, b->stream);
         if (e != hipSuccess) return e;
@@ -379,7 +383,7 @@ hipError_t restore_members(pdr_batch *b, Snapshot &sn, const std::vector<int32_t
         if (e == hipSuccess) e = snap_copy(sn, base + 1, c->Fsum, (size_t)c->m * 8, false, b->stream);
         if (e == hipSuccess) e = snap_copy(sn, base + 2, c->beta, (size_t)c->m * 8, false, b->stream);
         if (e == hipSuccess && c->method == PDR_GDM)
-            e = snap_copy(sn, base + 4, cur_v(c), mK * w, false, b->stream);
+            e = snap_copy(sn, base + 5, cur_v(c), mK * w, false, b->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -559,6 +563,13 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PDR_BCHECK(b, hipEventCreate(&e0));
     PDR_BCHECK(b, hipEventCreate(&e1));
+    // a failure once timing launches have run leaves the saved state restored
+    auto bail = [&](pdr_status why) -> pdr_status {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)snapshot_members(b, sn, all, false);
+        return why;
+    };
     std::vector<Tiling> best(b->buckets.size());
     hipError_t err = hipSuccess;
     for (size_t q = 0; q < b->buckets.size() && err == hipSuccess; ++q) {
@@ -611,11 +622,7 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     for (int64_t cand = 8192; cand <= 65536 && err == hipSuccess; cand *= 2) {
         b->height_budget = cand;
         st = build_maps(b);
-        if (st != PDR_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return st;
-        }
+        if (st != PDR_OK) return bail(st);
         err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
                                   b->height_unroll, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
@@ -656,30 +663,18 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     double t_tuned = 0.0, t_start = 0.0;
     if (err == hipSuccess) {
         st = apply(member_tl, best_budget);
-        if (st != PDR_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return st;
-        }
+        if (st != PDR_OK) return bail(st);
         err = time_passes(&t_tuned);
     }
     if (err == hipSuccess) {
         st = apply(start_tl, start_budget);
-        if (st != PDR_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return st;
-        }
+        if (st != PDR_OK) return bail(st);
         err = time_passes(&t_start);
     }
     const bool keep_tuned = err == hipSuccess && t_tuned < t_start;
     if (err == hipSuccess && keep_tuned) {
         st = apply(member_tl, best_budget);
-        if (st != PDR_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return st;
-        }
+        if (st != PDR_OK) return bail(st);
     }
     // each final bucket's arc launch on the saved state, for pdr_batch_buckets
     for (auto &bk : b->buckets) {

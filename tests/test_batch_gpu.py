@@ -164,6 +164,22 @@ def test_tuner_keeps_the_state_and_picks_covering_tilings(method):
             assert np.max(np.abs(b.member(q).flows() - st.f)) <= flow_tol(inst), q
 
 
+def test_tuner_keeps_a_wrapped_z_log():
+    """The tuner's timing passes write z-log entries; once the ring has wrapped
+    those slots hold retained evaluations, which must read the same after."""
+    insts = mixed_batch()[:4]
+    with pdr.Batch(insts, method=pdr.ESO, precision=pdr.FP64, z_log_capacity=64) as b:
+        b.sweep(150)
+        before = [b.member(q).z_log(150 - 64, 64) for q in range(len(insts))]
+        ctrl = [b.member(q).residual() for q in range(len(insts))]
+        b.tune(reps=2)
+        for q in range(len(insts)):
+            assert np.array_equal(b.member(q).z_log(150 - 64, 64), before[q]), q
+            res = b.member(q).residual()
+            assert res["evaluations"] == ctrl[q]["evaluations"]
+            assert res["sweeps_done"] == ctrl[q]["sweeps_done"]
+
+
 def test_batch_members_are_owned_by_the_batch():
     insts = converging_batch()[:3]
     with pdr.Batch(insts, method=pdr.ESO, precision=pdr.FP32_BULK) as b:
