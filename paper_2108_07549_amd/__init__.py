@@ -12,8 +12,11 @@ second runtime that does not see the device.
 
 Method: Liu, "A Localized Method for Multicommodity Flow Problem" (arXiv 2108.07549):
 heights from excess (Section 3.1), the exact edge subproblem (PDR-ESO,
-Section 4, Algorithms 1-2) and the adaptive-gradient update (PDR-AGD,
-Section 5.1, Algorithm 3).
+Section 4, Algorithms 1-2), the adaptive-gradient update (PDR-AGD,
+Section 5.1, Algorithm 3), its momentum variant (PDR-GDM, Section 5.2,
+Algorithm 4) and a capacity-enforcing loop for Section 6's formulation (CAP).
+Batches: ``Batch``; the reverse-mode gradient: ``Context.adjoint`` and
+``paper_2108_07549_amd.autograd``.
 """
 from __future__ import annotations
 
