@@ -172,7 +172,14 @@ void set_height_chunk(pdr_ctx *c)
     const int cap = c->req_height_chunk > 0 ? c->req_height_chunk : kHeightChunkAuto;
     c->g.height_cv = std::min<int>(cap, pow2ceil(nvec));
     c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : kHeightGridAuto;
-    c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : kHeightUnrollAuto;
+    int unroll = kHeightUnrollAuto;
+    if (c->precision == PDR_FP64) {
+        // few items per thread (a small instance): the kernel is latency-bound,
+        // and one batch of 8 rows covers most vertices' incidence lists
+        const int64_t items = (int64_t)c->n * nvec;
+        if (items < 16 * 256 * (int64_t)kHeightGridAuto) unroll = 8;
+    }
+    c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : unroll;
 }
 
 
