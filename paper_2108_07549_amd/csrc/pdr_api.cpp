@@ -171,14 +171,16 @@ void set_height_chunk(pdr_ctx *c)
     const int64_t nvec = c->Kp / vec_of(c->precision);
     const int cap = c->req_height_chunk > 0 ? c->req_height_chunk : kHeightChunkAuto;
     c->g.height_cv = std::min<int>(cap, pow2ceil(nvec));
-    c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : kHeightGridAuto;
-    int unroll = kHeightUnrollAuto;
-    if (c->precision == PDR_FP64) {
-        // few items per thread (a small instance): the kernel is latency-bound,
-        // and one batch of 8 rows covers most vertices' incidence lists
-        const int64_t items = (int64_t)c->n * nvec;
-        if (items < 16 * 256 * (int64_t)kHeightGridAuto) unroll = 8;
-    }
+    // A small instance leaves few height items per thread and the kernel is
+    // latency-bound: in FP64 one batch of 8 rows then covers most vertices'
+    // incidence lists; in FP32 (half the items) twice the resident grid lets
+    // the dispatcher even out the last round of items.
+    const int64_t items = (int64_t)c->n * nvec;
+    int grid = kHeightGridAuto, unroll = kHeightUnrollAuto;
+    if (c->precision == PDR_FP64 && items < 16 * 256 * (int64_t)kHeightGridAuto) unroll = 8;
+    if (c->precision != PDR_FP64 && items < 4 * 256 * (int64_t)kHeightGridAuto)
+        grid = 2 * kHeightGridAuto;
+    c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : grid;
     c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : unroll;
 }
 
