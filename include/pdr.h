@@ -12,7 +12,11 @@
  *
  * Conventions for every call:
  *  - No C++ exception crosses the ABI. Every call returns a pdr_status; the
- *    text of the last failure is returned by pdr_last_error.
+ *    text of the last failure is returned by pdr_last_error. A host memory
+ *    allocation that fails inside a call returns PDR_ERR_OOM; if the call
+ *    changes state (sweeps, solve, precision, state, adjoint, and the batch
+ *    calls that sweep, tune or switch precision), the object is then
+ *    poisoned as after a device error.
  *  - Host arrays passed in are read during the call only and stay owned by
  *    the caller. Output host arrays are owned by the caller.
  *  - The context owns all device memory it allocates. A context is not
@@ -38,7 +42,8 @@ typedef struct pdr_ctx pdr_ctx;
 typedef enum {
     PDR_OK = 0,
     PDR_ERR_INVALID = 1, /* bad argument or instance; nothing was changed */
-    PDR_ERR_OOM = 2,     /* device memory would not fit; nothing was allocated */
+    PDR_ERR_OOM = 2,     /* device memory would not fit (nothing was allocated),
+                            or a host allocation failed */
     PDR_ERR_DEVICE = 3,  /* a HIP call failed; the context is poisoned */
     PDR_ERR_STATE = 4,   /* call not valid in the context's current state */
     PDR_ERR_NUMERIC = 5  /* the objective became non-finite */

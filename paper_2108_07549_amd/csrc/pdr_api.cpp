@@ -69,12 +69,12 @@ hipError_t dalloc(pdr_ctx *c, T **p, size_t count)
 {
     *p = nullptr;
     if (count == 0) count = 1;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e == hipSuccess) {
-        c->allocs.push_back(q);
-        *p = static_cast<T *>(q);
-    }
+    c->allocs.push_back(nullptr);  // the slot first, so a failed push leaks nothing
+    hipError_t e = hipMalloc(&c->allocs.back(), count * sizeof(T));
+    if (e == hipSuccess)
+        *p = static_cast<T *>(c->allocs.back());
+    else
+        c->allocs.pop_back();
     return e;
 }
 
@@ -423,9 +423,12 @@ static pdr_status init_fail(pdr_ctx *c, pdr_status st, pdr_ctx **out)
     return st;
 }
 
-pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
-                    const int32_t *col, const double *u, int32_t K, const int32_t *s,
-                    const int32_t *t, const double *d, const pdr_options *opt_in)
+// *created receives the context as soon as it exists, so that the exception
+// barrier of pdr_init can free it if the body is left part way.
+static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
+                                const int32_t *col, const double *u, int32_t K,
+                                const int32_t *s, const int32_t *t, const double *d,
+                                const pdr_options *opt_in, pdr_ctx **created)
 {
     if (!out) {
         g_init_error = "out is NULL";
@@ -503,6 +506,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
         return invalid("height_chunk must be 0 or a power of two up to 256");
 
     pdr_ctx *c = new pdr_ctx();
+    *created = c;
     c->n = n;
     c->m = m;
     c->K = K;
@@ -712,7 +716,7 @@ pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
     return PDR_OK;
 }
 
-pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_target)
+static pdr_status pdr_sweep_body(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_target)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -749,8 +753,8 @@ pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_ta
     return PDR_OK;
 }
 
-pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t window,
-                     double floor_factor, int64_t *sweeps_fp32, int64_t *sweeps_fp64)
+static pdr_status pdr_solve_body(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t window,
+                                 double floor_factor, int64_t *sweeps_fp32, int64_t *sweeps_fp64)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -815,7 +819,7 @@ pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t wi
     return PDR_OK;
 }
 
-pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
+static pdr_status pdr_profile_sweeps_body(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -864,7 +868,7 @@ pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
     return PDR_OK;
 }
 
-pdr_status pdr_residual(pdr_ctx *c, pdr_residual_t *out)
+static pdr_status pdr_residual_body(pdr_ctx *c, pdr_residual_t *out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -903,7 +907,7 @@ pdr_status pdr_residual(pdr_ctx *c, pdr_residual_t *out)
     return PDR_OK;
 }
 
-pdr_status pdr_flows(pdr_ctx *c, double *host_out)
+static pdr_status pdr_flows_body(pdr_ctx *c, double *host_out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -924,7 +928,7 @@ pdr_status pdr_flows(pdr_ctx *c, double *host_out)
     return PDR_OK;
 }
 
-pdr_status pdr_flows_device(pdr_ctx *c, void *dev_out, int32_t fp64)
+static pdr_status pdr_flows_device_body(pdr_ctx *c, void *dev_out, int32_t fp64)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -935,7 +939,7 @@ pdr_status pdr_flows_device(pdr_ctx *c, void *dev_out, int32_t fp64)
     return PDR_OK;
 }
 
-pdr_status pdr_heights(pdr_ctx *c, double *host_out)
+static pdr_status pdr_heights_body(pdr_ctx *c, double *host_out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -950,7 +954,7 @@ pdr_status pdr_heights(pdr_ctx *c, double *host_out)
     return PDR_OK;
 }
 
-pdr_status pdr_learning_rates(pdr_ctx *c, double *host_out)
+static pdr_status pdr_learning_rates_body(pdr_ctx *c, double *host_out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -962,7 +966,7 @@ pdr_status pdr_learning_rates(pdr_ctx *c, double *host_out)
     return PDR_OK;
 }
 
-pdr_status pdr_velocities(pdr_ctx *c, double *host_out)
+static pdr_status pdr_velocities_body(pdr_ctx *c, double *host_out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -984,7 +988,7 @@ pdr_status pdr_velocities(pdr_ctx *c, double *host_out)
     return PDR_OK;
 }
 
-pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
+static pdr_status pdr_z_log_body(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -1007,7 +1011,7 @@ pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
     return PDR_OK;
 }
 
-pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
+static pdr_status pdr_set_precision_body(pdr_ctx *c, int32_t precision)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -1065,8 +1069,8 @@ pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
 
 extern "C" {
 
-pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, const double *v,
-                         int64_t t, double z_prev)
+static pdr_status pdr_set_state_body(pdr_ctx *c, const double *f, const double *beta,
+                                     const double *v, int64_t t, double z_prev)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -1126,8 +1130,8 @@ pdr_status pdr_tiling(const pdr_ctx *c, int32_t *lanes_per_arc, int32_t *vec_per
     return PDR_OK;
 }
 
-pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
-                       double *grad_u, double *grad_d)
+static pdr_status pdr_adjoint_body(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
+                                   double *grad_u, double *grad_d)
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
@@ -1147,10 +1151,9 @@ pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
         }
         hipError_t get(double **out, size_t count)
         {
-            void *q = nullptr;
-            hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(double));
-            if (e == hipSuccess) p.push_back(q);
-            *out = (double *)q;
+            p.push_back(nullptr);  // the slot first, so a failed push leaks nothing
+            hipError_t e = hipMalloc(&p.back(), (count ? count : 1) * sizeof(double));
+            *out = e == hipSuccess ? (double *)p.back() : nullptr;
             return e;
         }
     } bufs;
@@ -1221,7 +1224,7 @@ pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out,
     return PDR_OK;
 }
 
-pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
+static pdr_status pdr_measure_copy_body(int64_t bytes, int32_t iters, double *gbps)
 {
     if (bytes < 16 || iters < 1 || !gbps) {
         g_init_error = "pdr_measure_copy: need bytes >= 16, iters >= 1, gbps";
@@ -1263,12 +1266,134 @@ pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
     return PDR_OK;
 }
 
-void pdr_destroy(pdr_ctx *c)
+static void pdr_destroy_body(pdr_ctx *c)
 {
     if (!c || c->batch_member) return;  // a batch frees its own members
     (void)hipSetDevice(c->device);
     free_all(c);
     delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ exported entry points
+// Each runs its body behind the exception barrier (abi_guard).
+extern "C" {
+
+pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
+                    const int32_t *col, const double *u, int32_t K, const int32_t *s,
+                    const int32_t *t, const double *d, const pdr_options *opt_in)
+{
+    pdr_ctx *created = nullptr;
+    bool returned = false;
+    const pdr_status st = abi_guard(nullptr, nullptr, [&] {
+        const pdr_status r = pdr_init_body(out, n, m, row_ptr, col, u, K, s, t, d, opt_in,
+                                           &created);
+        returned = true;
+        return r;
+    });
+    if (!returned) {  // left part way by an exception: free what was built
+        if (created) {
+            free_all(created);
+            delete created;
+        }
+        if (out) *out = nullptr;
+    }
+    return st;
+}
+
+pdr_status pdr_sweep(pdr_ctx *c, int64_t max_sweeps, double eps_obj, double z_target)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_sweep_body(c, max_sweeps, eps_obj, z_target); });
+}
+
+pdr_status pdr_solve(pdr_ctx *c, double z_target, int64_t max_sweeps, int64_t window,
+                     double floor_factor, int64_t *sweeps_fp32, int64_t *sweeps_fp64)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_solve_body(c, z_target, max_sweeps, window, floor_factor, sweeps_fp32, sweeps_fp64); });
+}
+
+pdr_status pdr_profile_sweeps(pdr_ctx *c, int64_t sweeps, double *kernel_ms)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_profile_sweeps_body(c, sweeps, kernel_ms); });
+}
+
+pdr_status pdr_residual(pdr_ctx *c, pdr_residual_t *out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_residual_body(c, out); });
+}
+
+pdr_status pdr_flows(pdr_ctx *c, double *host_out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_flows_body(c, host_out); });
+}
+
+pdr_status pdr_flows_device(pdr_ctx *c, void *dev_out, int32_t fp64)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_flows_device_body(c, dev_out, fp64); });
+}
+
+pdr_status pdr_heights(pdr_ctx *c, double *host_out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_heights_body(c, host_out); });
+}
+
+pdr_status pdr_learning_rates(pdr_ctx *c, double *host_out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_learning_rates_body(c, host_out); });
+}
+
+pdr_status pdr_velocities(pdr_ctx *c, double *host_out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_velocities_body(c, host_out); });
+}
+
+pdr_status pdr_z_log(pdr_ctx *c, int64_t first, int64_t count, double *host_out)
+{
+    return abi_guard(c ? &c->err : nullptr, nullptr,
+                     [&] { return pdr_z_log_body(c, first, count, host_out); });
+}
+
+pdr_status pdr_set_precision(pdr_ctx *c, int32_t precision)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_set_precision_body(c, precision); });
+}
+
+pdr_status pdr_set_state(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                         int64_t t, double z_prev)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_set_state_body(c, f, beta, v, t, z_prev); });
+}
+
+pdr_status pdr_adjoint(pdr_ctx *c, int64_t T, int32_t checkpoint, double *z_out, double *grad_u,
+                       double *grad_d)
+{
+    return abi_guard(c ? &c->err : nullptr, c ? &c->poisoned : nullptr,
+                     [&] { return pdr_adjoint_body(c, T, checkpoint, z_out, grad_u, grad_d); });
+}
+
+pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps)
+{
+    return abi_guard(nullptr, nullptr, [&] { return pdr_measure_copy_body(bytes, iters, gbps); });
+}
+
+void pdr_destroy(pdr_ctx *c)
+{
+    try {
+        pdr_destroy_body(c);
+    } catch (...) {  // teardown cannot report; nothing may leave the ABI
+    }
 }
 
 }  // extern "C"

@@ -393,8 +393,10 @@ hipError_t restore_members(pdr_batch *b, Snapshot &sn, const std::vector<int32_t
 
 extern "C" {
 
-pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
-                          const pdr_options *opt_in)
+// *created receives the batch as soon as it exists, so that the exception
+// barrier of pdr_batch_init can free it if the body is left part way.
+static pdr_status pdr_batch_init_body(pdr_batch **out, int32_t B, const pdr_instance *insts,
+                                      const pdr_options *opt_in, pdr_batch **created)
 {
     if (!out) {
         g_init_error = "out is NULL";
@@ -408,7 +410,12 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
     pdr_options opt;
     pdr_default_options(&opt);
     if (opt_in) opt = *opt_in;
+    if (opt.height_blocks < 0 || opt.height_blocks > (1 << 20)) {
+        g_init_error = "height_blocks of a batch must be 0 or 1..2^20";
+        return PDR_ERR_INVALID;
+    }
     auto *b = new pdr_batch();
+    *created = b;
     b->B = B;
     b->method = opt.method;
     b->precision = opt.precision;
@@ -429,11 +436,6 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         if (e != hipSuccess) return init_fail_b(PDR_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
         b->own_stream = true;
-    }
-    if (opt.height_blocks < 0 || opt.height_blocks > (1 << 20)) {
-        g_init_error = "height_blocks of a batch must be 0 or 1..2^20";
-        delete b;
-        return PDR_ERR_INVALID;
     }
     pdr_options mo = opt;
     mo.stream = b->stream;
@@ -466,7 +468,7 @@ pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
     return PDR_OK;
 }
 
-pdr_status pdr_batch_member(pdr_batch *b, int32_t index, pdr_ctx **ctx)
+static pdr_status pdr_batch_member_body(pdr_batch *b, int32_t index, pdr_ctx **ctx)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -475,7 +477,7 @@ pdr_status pdr_batch_member(pdr_batch *b, int32_t index, pdr_ctx **ctx)
     return PDR_OK;
 }
 
-pdr_status pdr_batch_sweep(pdr_batch *b, int64_t max_sweeps, double eps_obj, double z_target)
+static pdr_status pdr_batch_sweep_body(pdr_batch *b, int64_t max_sweeps, double eps_obj, double z_target)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -513,7 +515,7 @@ pdr_status pdr_batch_sweep(pdr_batch *b, int64_t max_sweeps, double eps_obj, dou
     return PDR_OK;
 }
 
-pdr_status pdr_batch_stopped(pdr_batch *b, int32_t *n_stopped)
+static pdr_status pdr_batch_stopped_body(pdr_batch *b, int32_t *n_stopped)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -521,8 +523,8 @@ pdr_status pdr_batch_stopped(pdr_batch *b, int32_t *n_stopped)
     return count_stopped(b, n_stopped);
 }
 
-pdr_status pdr_batch_buckets(pdr_batch *b, int32_t max_buckets, pdr_bucket_info *out,
-                             int32_t *n_buckets)
+static pdr_status pdr_batch_buckets_body(pdr_batch *b, int32_t max_buckets, pdr_bucket_info *out,
+                                         int32_t *n_buckets)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -541,7 +543,7 @@ pdr_status pdr_batch_buckets(pdr_batch *b, int32_t max_buckets, pdr_bucket_info 
     return PDR_OK;
 }
 
-pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
+static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *height_blocks)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -698,7 +700,7 @@ pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
     return PDR_OK;
 }
 
-pdr_status pdr_batch_profile_sweeps(pdr_batch *b, int64_t sweeps, double *kernel_ms)
+static pdr_status pdr_batch_profile_sweeps_body(pdr_batch *b, int64_t sweeps, double *kernel_ms)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -730,7 +732,7 @@ pdr_status pdr_batch_profile_sweeps(pdr_batch *b, int64_t sweeps, double *kernel
     return PDR_OK;
 }
 
-pdr_status pdr_batch_set_precision(pdr_batch *b, int32_t precision)
+static pdr_status pdr_batch_set_precision_body(pdr_batch *b, int32_t precision)
 {
     pdr_status st;
     if (!busable(b, &st)) return st;
@@ -750,12 +752,92 @@ const char *pdr_batch_last_error(const pdr_batch *b)
     return b->err.c_str();
 }
 
-void pdr_batch_destroy(pdr_batch *b)
+static void pdr_batch_destroy_body(pdr_batch *b)
 {
     if (!b) return;
     (void)hipSetDevice(b->device);
     batch_free(b);
     delete b;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ exported entry points
+// Each runs its body behind the exception barrier (abi_guard).
+extern "C" {
+
+pdr_status pdr_batch_init(pdr_batch **out, int32_t B, const pdr_instance *insts,
+                          const pdr_options *opt_in)
+{
+    pdr_batch *created = nullptr;
+    bool returned = false;
+    const pdr_status st = abi_guard(nullptr, nullptr, [&] {
+        const pdr_status r = pdr_batch_init_body(out, B, insts, opt_in, &created);
+        returned = true;
+        return r;
+    });
+    if (!returned) {  // left part way by an exception: free what was built
+        if (created) {
+            try {
+                batch_free(created);
+            } catch (...) {
+            }
+            delete created;
+        }
+        if (out) *out = nullptr;
+    }
+    return st;
+}
+
+pdr_status pdr_batch_member(pdr_batch *b, int32_t index, pdr_ctx **ctx)
+{
+    return abi_guard(b ? &b->err : nullptr, nullptr,
+                     [&] { return pdr_batch_member_body(b, index, ctx); });
+}
+
+pdr_status pdr_batch_sweep(pdr_batch *b, int64_t max_sweeps, double eps_obj, double z_target)
+{
+    return abi_guard(b ? &b->err : nullptr, b ? &b->poisoned : nullptr,
+                     [&] { return pdr_batch_sweep_body(b, max_sweeps, eps_obj, z_target); });
+}
+
+pdr_status pdr_batch_stopped(pdr_batch *b, int32_t *n_stopped)
+{
+    return abi_guard(b ? &b->err : nullptr, nullptr,
+                     [&] { return pdr_batch_stopped_body(b, n_stopped); });
+}
+
+pdr_status pdr_batch_buckets(pdr_batch *b, int32_t max_buckets, pdr_bucket_info *out,
+                             int32_t *n_buckets)
+{
+    return abi_guard(b ? &b->err : nullptr, nullptr,
+                     [&] { return pdr_batch_buckets_body(b, max_buckets, out, n_buckets); });
+}
+
+pdr_status pdr_batch_tune(pdr_batch *b, int32_t reps, int64_t *height_blocks)
+{
+    return abi_guard(b ? &b->err : nullptr, b ? &b->poisoned : nullptr,
+                     [&] { return pdr_batch_tune_body(b, reps, height_blocks); });
+}
+
+pdr_status pdr_batch_profile_sweeps(pdr_batch *b, int64_t sweeps, double *kernel_ms)
+{
+    return abi_guard(b ? &b->err : nullptr, b ? &b->poisoned : nullptr,
+                     [&] { return pdr_batch_profile_sweeps_body(b, sweeps, kernel_ms); });
+}
+
+pdr_status pdr_batch_set_precision(pdr_batch *b, int32_t precision)
+{
+    return abi_guard(b ? &b->err : nullptr, b ? &b->poisoned : nullptr,
+                     [&] { return pdr_batch_set_precision_body(b, precision); });
+}
+
+void pdr_batch_destroy(pdr_batch *b)
+{
+    try {
+        pdr_batch_destroy_body(b);
+    } catch (...) {  // teardown cannot report; nothing may leave the ABI
+    }
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -99,4 +101,36 @@ pdr_status set_precision_impl(pdr_ctx *c, int32_t precision);
 // Choose the sweep kernels' cache hints for the current storage precision
 // (batch members always stream).
 void set_cache_policy(pdr_ctx *c);
+
+// Exception barrier of the C ABI: every exported entry point runs its body
+// through abi_guard, so no C++ exception (in practice std::bad_alloc from a
+// host container) leaves the library. A failed host allocation returns
+// PDR_ERR_OOM, any other exception PDR_ERR_INVALID; the text goes to *err (to
+// the calling thread's init error when err is NULL). A call that may have
+// changed the object's state part way passes the object's poisoned flag,
+// which is then set: later calls answer PDR_ERR_DEVICE until it is destroyed.
+template <typename Body>
+pdr_status abi_guard(std::string *err, bool *poisoned, Body &&body) noexcept
+{
+    pdr_status st = PDR_ERR_INVALID;
+    const char *what = "unexpected C++ exception";
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        st = PDR_ERR_OOM;
+        what = "host memory allocation failed";
+    } catch (const std::length_error &) {
+        st = PDR_ERR_OOM;
+        what = "host allocation larger than the address space";
+    } catch (...) {
+    }
+    if (poisoned) *poisoned = true;
+    try {
+        std::string &dst = err ? *err : g_init_error;
+        dst = what;
+        if (poisoned) dst += " (the object is poisoned; destroy it)";
+    } catch (...) {
+    }
+    return st;
+}
 }  // namespace pdr_host

@@ -29,6 +29,37 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def exported_definitions():
+    """Body text of every exported (column-0, non-static) definition of a
+    declared entry point in the library sources."""
+    out = {}
+    for fn in ("pdr_api.cpp", "pdr_batch.cpp"):
+        with open(os.path.join(ROOT, "paper_2108_07549_amd", "csrc", fn)) as fh:
+            text = fh.read()
+        for mt in re.finditer(r"^(?:pdr_status|void|const char \*)\s*(pdr_[a-z_]+)\(", text, re.M):
+            start = text.index("\n{", mt.end())
+            end = text.index("\n}", start)
+            out[mt.group(1)] = text[start:end]
+    return out
+
+
+def test_every_entry_point_runs_behind_the_exception_barrier():
+    """No C++ exception may cross the C ABI: every declared entry point that
+    can allocate host memory wraps its body in abi_guard (or, for the destroy
+    calls, a catch-all)."""
+    defs = exported_definitions()
+    no_alloc = {"pdr_default_options", "pdr_last_error", "pdr_batch_last_error", "pdr_tiling"}
+    for name in declared_symbols():
+        assert name in defs, name
+        if name in no_alloc:
+            continue
+        body = defs[name]
+        if name.endswith("destroy"):
+            assert "catch (...)" in body, name
+        else:
+            assert "abi_guard(" in body, name
+
+
 def test_default_options_are_the_papers_settings():
     o = pdr.default_options()
     assert o.method == pdr.ESO and o.precision == pdr.FP64
