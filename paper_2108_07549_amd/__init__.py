@@ -266,7 +266,15 @@ class Context:
         return out
 
     def flows_device(self, out_tensor, fp64: bool = True):
-        """Write flows into a caller-owned device tensor of m*K elements."""
+        """Write flows into a caller-owned device tensor of m*K elements
+        (float64 when fp64, else float32), contiguous, on the context's GPU."""
+        import torch
+        want = torch.float64 if fp64 else torch.float32
+        if not out_tensor.is_cuda or out_tensor.dtype != want:
+            raise ValueError(f"flows_device needs a {want} GPU tensor")
+        if not out_tensor.is_contiguous() or out_tensor.numel() < self.m * self.K:
+            raise ValueError(f"flows_device needs a contiguous tensor of at least "
+                             f"m*K = {self.m * self.K} elements")
         self._check(lib().pdr_flows_device(self._h, C.c_void_p(out_tensor.data_ptr()),
                                            1 if fp64 else 0))
         return out_tensor

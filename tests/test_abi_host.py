@@ -185,3 +185,17 @@ def test_autograd_function_checks_dtypes_before_any_call():
     with pytest.raises(TypeError):
         residual_after_sweeps(inst, torch.tensor(inst.u, dtype=torch.float32),
                               torch.tensor(inst.d, dtype=torch.float64), 4)
+
+
+def test_flows_device_checks_the_tensor_before_any_call():
+    """A tensor the library would write past, or read as the wrong type, is
+    refused by the binding before any library call."""
+    import ctypes
+    import torch
+    c = pdr.Context.__new__(pdr.Context)
+    c._h, c._keep = ctypes.c_void_p(), None
+    c.n, c.m, c.K = 4, 6, 3
+    for t, fp64 in ((torch.empty(18, dtype=torch.float64), True),
+                    (torch.empty(18, dtype=torch.float32), False)):
+        with pytest.raises(ValueError):
+            c.flows_device(t, fp64)

@@ -329,6 +329,18 @@ with pdr.Context.from_instance(inst, method=pdr.ESO) as c:
     c.flows_device(out64, True)
     c.flows_device(out32, False)
     torch.cuda.synchronize()
+    # the binding refuses a tensor the library would write past or misread
+    for bad, fp64 in ((torch.empty(inst.m * inst.K - 1, dtype=torch.float64, device="cuda"), True),
+                      (out32, True), (out64, False),
+                      (torch.empty(inst.m * inst.K, dtype=torch.float64), True),
+                      (torch.empty(2 * inst.m * inst.K, dtype=torch.float64, device="cuda")[::2],
+                       True)):
+        try:
+            c.flows_device(bad, fp64)
+        except ValueError:
+            pass
+        else:
+            raise AssertionError("flows_device accepted a bad tensor")
 assert np.array_equal(out64.cpu().numpy().reshape(inst.m, inst.K), host)
 assert np.array_equal(out32.cpu().numpy().reshape(inst.m, inst.K), host.astype(np.float32))
 s = torch.cuda.Stream()
