@@ -205,8 +205,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid100_k10000")
-    ap.add_argument("--cpu-sweeps", type=int, default=32,
-                    help="oracle sweeps of the CPU baseline (about 10 s on 16 host threads)")
+    ap.add_argument("--cpu-sweeps", type=int, default=48,
+                    help="oracle sweeps of the CPU baseline (about 13 s on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=2 << 30,
