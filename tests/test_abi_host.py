@@ -199,3 +199,37 @@ def test_flows_device_checks_the_tensor_before_any_call():
                     (torch.empty(18, dtype=torch.float32), False)):
         with pytest.raises(ValueError):
             c.flows_device(t, fp64)
+
+
+HOST_OOM = r"""
+import ctypes as C, resource, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+import paper_2108_07549_amd as pdr
+L = pdr.lib()
+n = 50_000_000  # init's first host arrays then need 200 MB
+rp = np.zeros(n + 1, np.int64)
+one = np.zeros(1, np.int32)
+s, t, ud = np.array([0], np.int32), np.array([1], np.int32), np.ones(1)
+vm = [int(x.split()[1]) for x in open("/proc/self/status") if x.startswith("VmSize")][0] * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (64 << 20), resource.RLIM_INFINITY))
+h = C.c_void_p()
+p = lambda a: a.ctypes.data_as(C.c_void_p)
+st = L.pdr_init(C.byref(h), n, 0, p(rp), p(one), p(ud), 1, p(s), p(t), p(ud), None)
+print(st, h.value is None, L.pdr_last_error(None).decode())
+"""
+
+
+def test_host_allocation_failure_is_a_status_not_an_exception():
+    """Under an address-space limit, pdr_init's host arrays cannot be allocated:
+    the call returns PDR_ERR_OOM with its text (a C++ exception crossing the C
+    ABI would abort the process). Runs in a child process with the limit set
+    after the library is loaded; init fails before any device call."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", HOST_OOM.format(root=ROOT)], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    st, null_handle, msg = r.stdout.strip().split(" ", 2)
+    assert int(st) == 2 and null_handle == "True"
+    assert "host memory allocation failed" in msg
