@@ -188,15 +188,28 @@ def time_adjoint(pdr, inst, T, checkpoint, forward_ms):
                 max_abs_grad_u=float(np.max(np.abs(gu))), max_abs_grad_d=float(np.max(np.abs(gd))))
 
 
-def cpu_baseline(inst, sweeps):
+def cpu_baseline(inst, sweeps, single_sweeps):
     import oracle
     t0 = time.perf_counter()
     oracle.run(inst, oracle.ESO, sweeps)
     sec = time.perf_counter() - t0
-    return dict(value=inst.m * inst.K * sweeps / sec, unit="updates/s",
-                cores=oracle.num_threads(), kind="oracle",
-                sample=f"{sweeps} PDR-ESO FP64 sweeps of the full workload from f = 0 "
-                       f"({sec:.1f} s)")
+    out = dict(value=inst.m * inst.K * sweeps / sec, unit="updates/s",
+               cores=oracle.num_threads(), kind="oracle",
+               sample=f"{sweeps} PDR-ESO FP64 sweeps of the full workload from f = 0 "
+                      f"({sec:.1f} s)")
+    if single_sweeps > 0:
+        nt = oracle.num_threads()
+        oracle.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.run(inst, oracle.ESO, single_sweeps)
+            sec1 = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(nt)
+        out["single_thread"] = dict(
+            value=inst.m * inst.K * single_sweeps / sec1, unit="updates/s", cores=1,
+            sample=f"{single_sweeps} sweeps from f = 0 ({sec1:.1f} s)")
+    return out
 
 
 def main():
@@ -207,6 +220,8 @@ def main():
     ap.add_argument("--workload", default="grid100_k10000")
     ap.add_argument("--cpu-sweeps", type=int, default=48,
                     help="oracle sweeps of the CPU baseline (about 13 s on 16 host threads)")
+    ap.add_argument("--cpu-single-sweeps", type=int, default=8,
+                    help="oracle sweeps of the one-thread CPU figure, about 10 s (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=2 << 30,
@@ -326,7 +341,7 @@ def main():
         out["batch"] = bat
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_sweeps} oracle sweeps", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps, args.cpu_single_sweeps)
     print(json.dumps(out), flush=True)
 
 

@@ -51,6 +51,7 @@ def lib():
         P = C.c_void_p
         i32, i64, dbl = C.c_int32, C.c_int64, C.c_double
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_degrees.argtypes = [i32, i32, P, P, P]
         L.orc_excess.argtypes = [i32, i32, P, P, i32, P, P, P, P, P, P]
         L.orc_congestion.argtypes = [i32, i32, P, P, P, P]
@@ -88,6 +89,11 @@ def _c(a, dt):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(nt: int) -> None:
+    """Threads of later oracle calls (for timing; results do not depend on it)."""
+    lib().orc_set_num_threads(int(nt))
 
 
 def degrees(inst) -> np.ndarray:

@@ -56,6 +56,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Thread count of later parallel regions (timing only: no result depends on it). */
+void orc_set_num_threads(int nt)
+{
+#ifdef _OPENMP
+    if (nt > 0) omp_set_num_threads(nt);
+#else
+    (void)nt;
+#endif
+}
+
 /* Tail of every arc. */
 void orc_tails(int32_t n, int32_t m, const int64_t *row_ptr, int32_t *tails)
 {

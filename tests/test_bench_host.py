@@ -42,3 +42,13 @@ def test_stale_or_missing_counters_give_no_traffic(tmp_path, monkeypatch):
     assert bench.measured_traffic("absent") is None
     monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "none.json"))
     assert bench.measured_traffic("k") is None
+
+
+def test_cpu_baseline_reports_both_thread_counts_and_restores_them():
+    import oracle
+    from gen.instance import recipe_grid4_k8
+    nt = oracle.num_threads()
+    out = bench.cpu_baseline(recipe_grid4_k8(), 3, 2)
+    assert out["kind"] == "oracle" and out["cores"] == nt and out["value"] > 0
+    assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
+    assert oracle.num_threads() == nt
