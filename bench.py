@@ -107,26 +107,44 @@ def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=2048, 
                 precision_final="fp64" if n64 or precision == pdr.FP64 else "fp32")
 
 
-def time_to_target(pdr, inst, method, precision, target, cap, window=512):
+def time_to_target(pdr, inst, method, precision, target, cap, window=512, chunk=1_000_000,
+                   tag=""):
     """From f = 0, pdr_solve to z <= target (FP32-bulk runs widen to FP64 and
-    polish by its rule) in one call; the wall time, the passes in each
-    precision, and the first pass at which z fell to each decade of a ladder."""
+    polish by its rule); the wall time, the passes in each precision, and the
+    first pass at which z fell to each decade of a ladder. Runs longer than
+    `chunk` passes are split into pdr_solve calls of `chunk` passes, with a
+    progress line after each (the hand-over rule then restarts its windows)."""
+    ladder = {str(t): None for t in (1e-2, 1e-4, 1e-6, 1e-8)}
     with pdr.Context.from_instance(inst, method=method, precision=precision) as ctx:
         pdr.device_synchronize()
         t0 = time.perf_counter()
-        n32, n64 = ctx.solve(target, cap, window)
-        pdr.device_synchronize()
-        sec = time.perf_counter() - t0
-        res = ctx.residual()
-        ev = res["evaluations"]
-        first = max(0, ev - (1 << 20))  # the z log keeps the last 2^20 evaluations
-        zl = ctx.z_log(first, ev - first)
-    ladder = {}
-    for thr in (1e-2, 1e-4, 1e-6, 1e-8):
-        hit = np.nonzero(zl <= thr)[0]
-        ladder[str(thr)] = int(first + hit[0]) if hit.size else None
+        n32 = n64 = 0
+        ev0 = 0
+        while True:
+            a, b = ctx.solve(target, min(chunk, cap - n32 - n64), window)
+            pdr.device_synchronize()
+            n32, n64 = n32 + a, n64 + b
+            sec = time.perf_counter() - t0
+            res = ctx.residual()
+            ev = res["evaluations"]
+            # the z log keeps the last 2^20 evaluations (chunk <= 2^20 covers them all)
+            first = max(ev0, ev - (1 << 20))
+            zl = ctx.z_log(first, ev - first)
+            for thr in ladder:
+                if ladder[thr] is None:
+                    hit = np.nonzero(zl <= float(thr))[0]
+                    if hit.size:
+                        ladder[thr] = int(first + hit[0])
+            ev0 = ev
+            done = res["z"] <= target or n32 + n64 >= cap or a + b == 0
+            if not done:
+                print(f"[bench] ttr {tag}: {n32} + {n64} passes, z {res['z']:.3e}, {sec:.0f} s",
+                      file=sys.stderr, flush=True)
+            else:
+                break
     return dict(seconds=sec, sweeps_fp32=n32, sweeps_fp64=n64, z_final=res["z"],
-                reached=bool(res["z"] <= target), verdict=res["verdict"], first_pass_at=ladder)
+                reached=bool(res["z"] <= target), verdict=res["verdict"], first_pass_at=ladder,
+                solve_calls_of=chunk)
 
 
 def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
@@ -321,7 +339,8 @@ def main():
             for pname, prec in (("fp64", pdr.FP64), ("fp32_polish", pdr.FP32_BULK)):
                 print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: running", file=sys.stderr,
                       flush=True)
-                r = time_to_target(pdr, tinst, names[mname], prec, 1e-8, args.ttr_cap)
+                r = time_to_target(pdr, tinst, names[mname], prec, 1e-8, args.ttr_cap,
+                                   tag=f"{args.ttr_workload} {mname} {pname}")
                 print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: {r}", file=sys.stderr,
                       flush=True)
                 full[f"{mname}_{pname}"] = r
