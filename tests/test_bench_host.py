@@ -52,3 +52,60 @@ def test_cpu_baseline_reports_both_thread_counts_and_restores_them():
     assert out["kind"] == "oracle" and out["cores"] == nt and out["value"] > 0
     assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
     assert oracle.num_threads() == nt
+
+
+class _FakeCtx:
+    """Stands in for a context: z falls by 10x per pass from 1, one z-log entry
+    per pass, FP32 for the first 4 passes then FP64."""
+
+    def __init__(self):
+        self.ev = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+    def z(self, i):
+        return 10.0 ** (-i)
+
+    def solve(self, target, max_sweeps, window):
+        a = b = 0
+        while a + b < max_sweeps and not self.z(self.ev) <= target:
+            self.ev += 1
+            if self.ev <= 4:
+                a += 1
+            else:
+                b += 1
+        return a, b
+
+    def residual(self):
+        return {"evaluations": self.ev, "z": self.z(self.ev), "verdict": "feasible"}
+
+    def z_log(self, first, count):
+        import numpy as np
+        return np.array([self.z(i + 1) for i in range(first, first + count)])
+
+
+class _FakePdr:
+    @staticmethod
+    def device_synchronize():
+        pass
+
+    class Context:
+        @staticmethod
+        def from_instance(inst, **kw):
+            return _FakeCtx()
+
+
+def test_time_to_target_chunks_long_runs_and_keeps_the_ladder():
+    """Runs split into solve calls of `chunk` passes report the same totals and
+    ladder as one call (first pass at or below each decade)."""
+    one = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 100, chunk=100)
+    many = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 100, chunk=3)
+    for r in (one, many):
+        assert r["reached"] and (r["sweeps_fp32"], r["sweeps_fp64"]) == (4, 4)
+        assert r["first_pass_at"] == {"0.01": 1, "0.0001": 3, "1e-06": 5, "1e-08": 7}
+    capped = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 5, chunk=2)
+    assert not capped["reached"] and capped["sweeps_fp32"] + capped["sweeps_fp64"] == 5
