@@ -30,12 +30,21 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "PDR edge×commodity updates/s + time-to-residual 1e-8, FP32+polish vs FP64"
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2108_07549_amd", "csrc", "pdr_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2108_07549_amd", "csrc")
+
+
+def kernel_sources():
+    """The device code: the shared header and every kernel translation unit."""
+    names = sorted(n for n in os.listdir(CSRC) if n.startswith("pdr_k_") and n.endswith(".hip"))
+    return [os.path.join(CSRC, n) for n in ["pdr_device.h", *names]]
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in kernel_sources():
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(key: str):

@@ -1,5 +1,8 @@
 """Build libpdr.so (HIP for gfx950) in-tree with hipcc.
 
+Each translation unit is compiled to an object in parallel (the kernel
+instantiations dominate the build), then the objects are linked.
+
 Usage: python -m paper_2108_07549_amd.build
 """
 from __future__ import annotations
@@ -10,26 +13,50 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpdr.so")
-SOURCES = [os.path.join(PKG, "csrc", "pdr_kernels.hip"), os.path.join(PKG, "csrc", "pdr_api.cpp"),
-           os.path.join(PKG, "csrc", "pdr_batch.cpp")]
+OBJDIR = os.path.join(PKG, "_build")
+SOURCES = ["pdr_k_core.hip", "pdr_k_eso.hip", "pdr_k_agd.hip", "pdr_k_misc.hip",
+           "pdr_k_batch.hip", "pdr_api.cpp", "pdr_batch.cpp"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1))
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cmds = []
+    objs = []
+    for s in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o")
+        objs.append(obj)
+        cmds.append([hipcc, *HIPCC_FLAGS, *inc, "-c", "-o", obj, os.path.join(CSRC, s)])
+    running = []
+    failed = None
+    pending = list(cmds)
+    while pending or running:
+        while pending and len(running) < jobs:
+            cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((cmd, subprocess.Popen(cmd)))
+        cmd, proc = running.pop(0)
+        if proc.wait() != 0 and failed is None:
+            failed = cmd
+    if failed is not None:
+        raise subprocess.CalledProcessError(1, failed)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(PKG, "csrc"), "-o", tmp, *SOURCES]
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

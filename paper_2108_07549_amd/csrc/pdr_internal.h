@@ -1,5 +1,6 @@
 // Internal interface between the host library (pdr_api.cpp) and the HIP
-// kernels (pdr_kernels.hip). Not part of the public ABI.
+// kernels (pdr_device.h and the pdr_k_*.hip translation units). Not part of
+// the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -139,6 +140,9 @@ hipError_t launch_adj_seed(const DevGraph &g, const double *Fsum, const double *
 // entry dz/df of the pass's output is cbar + Dbar_head - Dbar_tail; on return
 // cbar and Dbar hold the pass's own, and ubar and dbar have accumulated. tl is
 // the tiling the forward arc kernel used.
+// The vertex half of launch_adj_pass (Dbar from cbar, then dbar).
+hipError_t launch_adj_vertex(const DevGraph &g, const double *cbar, double *Dbar, double *dbar,
+                             hipStream_t st);
 hipError_t launch_adj_pass(const DevGraph &g, Tiling tl, const double *f, const double *h,
                            double *cbar, double *Dbar, double *ubar, double *dbar, hipStream_t st);
 
