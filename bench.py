@@ -215,6 +215,37 @@ def time_adjoint(pdr, inst, T, checkpoint, forward_ms):
                 max_abs_grad_u=float(np.max(np.abs(gu))), max_abs_grad_d=float(np.max(np.abs(gd))))
 
 
+def host_identity() -> dict:
+    """The host CPU as /proc/cpuinfo names it: model, logical CPUs this process
+    may use, and physical cores (distinct (package, core) pairs)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                elif not key and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return dict(cpu_model=model, logical_cpus_usable=usable, logical_cpus=os.cpu_count(),
+                physical_cores=len(cores) or None)
+
+
 def cpu_baseline(inst, sweeps, single_sweeps):
     import oracle
     t0 = time.perf_counter()
@@ -223,7 +254,7 @@ def cpu_baseline(inst, sweeps, single_sweeps):
     out = dict(value=inst.m * inst.K * sweeps / sec, unit="updates/s",
                cores=oracle.num_threads(), kind="oracle",
                sample=f"{sweeps} PDR-ESO FP64 sweeps of the full workload from f = 0 "
-                      f"({sec:.1f} s)")
+                      f"({sec:.1f} s)", host=host_identity())
     if single_sweeps > 0:
         nt = oracle.num_threads()
         oracle.set_num_threads(1)
@@ -307,7 +338,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "K": K, "method": "eso",
-                   "precision": "fp64", "load_factor": inst.meta.get("load_factor"),
+                   "precision": "fp64",
+                   # the demands are scaled to this load factor against an explicit
+                   # routing; the certified load factor lies in lf_bracket
+                   "load_factor_target": inst.meta.get("load_factor"),
                    "lf_bracket": inst.meta.get("lf_bracket"), "tiling": head["tiling"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -195,18 +195,31 @@ pdr_status pdr_solve(pdr_ctx *ctx, double z_target, int64_t max_sweeps, int64_t 
  * Returns PDR_ERR_NUMERIC (and fills *out) if z is not finite. */
 pdr_status pdr_residual(pdr_ctx *ctx, pdr_residual_t *out);
 
-/* Copy the current flows as FP64 into host_out[m*K] (synchronizes). */
+/* Copy the current pseudo-flow f (Section 3.1: f_ek >= 0 of every commodity
+ * k on every arc e, not necessarily conserving) as FP64 into host_out[m*K],
+ * m x K row-major in the caller's arc order (synchronizes). */
 pdr_status pdr_flows(pdr_ctx *ctx, double *host_out);
 
-/* Write the current flows into caller-owned device memory dev_out[m*K] on
- * the context stream, as FP64 if fp64 != 0 else FP32 (no host sync). */
+/* Write the current pseudo-flow (Section 3.1) into caller-owned device
+ * memory dev_out[m*K] (m x K row-major, caller's arc order), as FP64 if
+ * fp64 != 0 else FP32. The write is enqueued on the context stream after all
+ * work already enqueued there and the call returns without a host sync: a
+ * reader on another stream must wait for the context stream first (an event
+ * recorded on the stream pdr_stream returns, or a device synchronization).
+ * The Python binding does this against torch's current stream. */
 pdr_status pdr_flows_device(pdr_ctx *ctx, void *dev_out, int32_t fp64);
 
-/* Copy the FP64 heights h[n*K] of the current flows (Expression 4) to the
- * host (synchronizes). */
+/* The HIP stream the context runs on (hipStream_t as void*): the caller's
+ * pdr_options.stream, or the one the library created. */
+pdr_status pdr_stream(const pdr_ctx *ctx, void **stream);
+
+/* Copy the FP64 heights h[n*K] of the current flows (Expressions 2-4:
+ * h_ik = Delta_ik / delta_i with Delta the excess of Section 3.1), n x K
+ * row-major, to the host (synchronizes). */
 pdr_status pdr_heights(pdr_ctx *ctx, double *host_out);
 
-/* Copy the AGD/GDM learning rates beta[m] to the host (synchronizes). */
+/* Copy the per-arc learning rates beta[m] of Algorithms 3 and 4 (caller's
+ * arc order) to the host (synchronizes). */
 pdr_status pdr_learning_rates(pdr_ctx *ctx, double *host_out);
 
 /* Copy the GDM velocities v[m*K] (Algorithm 4) as FP64 to the host
@@ -219,16 +232,24 @@ pdr_status pdr_velocities(pdr_ctx *ctx, double *host_out);
  * PDR_ERR_INVALID. */
 pdr_status pdr_z_log(pdr_ctx *ctx, int64_t first, int64_t count, double *host_out);
 
-/* Switch the storage precision. FP32_BULK -> FP64 widens the current flows
- * exactly (the FP64 "polish" phase); FP64 -> FP32_BULK rounds them. The
- * iteration counter, z_prev and learning rates are kept. A batch member
- * returns PDR_ERR_STATE: its batch switches with pdr_batch_set_precision. */
+/* Switch the storage precision of the pseudo-flow f of Section 3.1 (and of
+ * the GDM velocities of Algorithm 4). FP32_BULK -> FP64 widens the current
+ * flows exactly (the FP64 "polish" phase); FP64 -> FP32_BULK rounds them. The
+ * iteration counter, z_prev and learning rates are kept. PDR_ERR_INVALID for
+ * an unknown precision or a row no arc kernel holds in the new precision (the
+ * state is then unchanged). A batch member returns PDR_ERR_STATE: its batch
+ * switches with pdr_batch_set_precision. */
 pdr_status pdr_set_precision(pdr_ctx *ctx, int32_t precision);
 
-/* Replace the run state: flows f[m*K] (FP64, >= 0, finite), AGD/GDM rates
- * beta[m] (may be NULL to keep), GDM velocities v[m*K] (finite; may be NULL to
- * keep; ignored by other methods), iteration counter t and z_prev (+inf to
- * restart the stop test). Used to resume a saved run. */
+/* Replace the run state: the pseudo-flow f[m*K] (Section 3.1; FP64, m x K
+ * row-major in the caller's arc order, >= 0, finite; rounded to FP32 in
+ * PDR_FP32_BULK), the learning rates beta[m] of Algorithms 3-4 (may be NULL
+ * to keep), the GDM velocities v[m*K] of Algorithm 4 (finite; may be NULL to
+ * keep; ignored by other methods), the iteration counter t and z_prev of
+ * Algorithm 1's stop test (+inf to restart it). Used to resume a saved run.
+ * PDR_ERR_INVALID for a NULL f (m > 0), t < 0, a NaN z_prev or an entry out
+ * of range (nothing is changed); PDR_ERR_OOM if the staging buffer does not
+ * fit. */
 pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, const double *v,
                          int64_t t, double z_prev);
 

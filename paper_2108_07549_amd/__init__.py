@@ -35,7 +35,7 @@ STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVIC
           4: "PDR_ERR_STATE", 5: "PDR_ERR_NUMERIC"}
 
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
-           "pdr_flows_device", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
+           "pdr_flows_device", "pdr_stream", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
            "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
            "pdr_tiling", "pdr_adjoint", "pdr_destroy", "pdr_last_error",
            "pdr_batch_init", "pdr_batch_sweep", "pdr_batch_member", "pdr_batch_stopped",
@@ -113,6 +113,7 @@ def lib():
         L.pdr_residual.argtypes = [P, C.POINTER(Residual)]
         L.pdr_flows.argtypes = [P, P]
         L.pdr_flows_device.argtypes = [P, P, i32]
+        L.pdr_stream.argtypes = [P, C.POINTER(P)]
         L.pdr_heights.argtypes = [P, P]
         L.pdr_learning_rates.argtypes = [P, P]
         L.pdr_velocities.argtypes = [P, P]
@@ -265,9 +266,19 @@ class Context:
         self._check(lib().pdr_flows(self._h, _ptr(out)))
         return out
 
+    def stream_handle(self) -> int:
+        """The HIP stream (as an integer handle) the context's work runs on."""
+        out = C.c_void_p()
+        self._check(lib().pdr_stream(self._h, C.byref(out)))
+        return int(out.value or 0)
+
     def flows_device(self, out_tensor, fp64: bool = True):
         """Write flows into a caller-owned device tensor of m*K elements
-        (float64 when fp64, else float32), contiguous, on the context's GPU."""
+        (float64 when fp64, else float32), contiguous, on the context's GPU.
+        The write is ordered after torch's current stream's earlier work on
+        the tensor, and later work on that stream sees the flows: the context
+        stream waits for torch's stream before the write, and torch's stream
+        waits for the context stream after it (events, no host sync)."""
         import torch
         want = torch.float64 if fp64 else torch.float32
         if not out_tensor.is_cuda or out_tensor.dtype != want:
@@ -275,8 +286,15 @@ class Context:
         if not out_tensor.is_contiguous() or out_tensor.numel() < self.m * self.K:
             raise ValueError(f"flows_device needs a contiguous tensor of at least "
                              f"m*K = {self.m * self.K} elements")
+        cur = torch.cuda.current_stream(out_tensor.device)
+        mine = torch.cuda.ExternalStream(self.stream_handle(), device=out_tensor.device)
+        same = mine.cuda_stream == cur.cuda_stream
+        if not same:
+            mine.wait_stream(cur)
         self._check(lib().pdr_flows_device(self._h, C.c_void_p(out_tensor.data_ptr()),
                                            1 if fp64 else 0))
+        if not same:
+            cur.wait_stream(mine)
         return out_tensor
 
     def heights(self) -> np.ndarray:

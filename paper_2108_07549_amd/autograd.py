@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import ESO, FP64, Context
+from . import ESO, FP64, Context, PdrError
 
 
 class ResidualAfterSweeps(torch.autograd.Function):
@@ -32,10 +32,19 @@ class ResidualAfterSweeps(torch.autograd.Function):
         n, row_ptr, col, s, t = graph
         uh = u.detach().to("cpu").numpy()
         dh = d.detach().to("cpu").numpy()
+        want_grad = any(ctx.needs_input_grad[:2])
         with Context(n, row_ptr, col, uh, s, t, dh, method=ESO, precision=FP64) as c:
-            z, gu, gd = c.adjoint(int(T), int(checkpoint))
-        ctx.save_for_backward(torch.from_numpy(np.ascontiguousarray(gu)).to(u.device),
-                              torch.from_numpy(np.ascontiguousarray(gd)).to(d.device))
+            if want_grad:
+                z, gu, gd = c.adjoint(int(T), int(checkpoint))
+            else:  # no gradient wanted: the T passes and the objective only
+                c.sweep(int(T))
+                res = c.residual()
+                if res["status"] != "PDR_OK":
+                    raise PdrError(5 if res["status"] == "PDR_ERR_NUMERIC" else 3, "pdr_residual")
+                z = res["z"]
+        if want_grad:
+            ctx.save_for_backward(torch.from_numpy(np.ascontiguousarray(gu)).to(u.device),
+                                  torch.from_numpy(np.ascontiguousarray(gd)).to(d.device))
         return torch.tensor(z, dtype=torch.float64, device=u.device)
 
     @staticmethod

@@ -1121,6 +1121,13 @@ static pdr_status pdr_set_state_body(pdr_ctx *c, const double *f, const double *
     return push_ctrl(c);
 }
 
+static pdr_status pdr_stream_body(const pdr_ctx *c, void **stream)
+{
+    if (!c || !stream) return PDR_ERR_INVALID;
+    *stream = (void *)c->stream;
+    return PDR_OK;
+}
+
 pdr_status pdr_tiling(const pdr_ctx *c, int32_t *lanes_per_arc, int32_t *vec_per_lane, int32_t *Kp)
 {
     if (!c) return PDR_ERR_INVALID;
@@ -1337,6 +1344,11 @@ pdr_status pdr_flows_device(pdr_ctx *c, void *dev_out, int32_t fp64)
 {
     return abi_guard(c ? &c->err : nullptr, nullptr,
                      [&] { return pdr_flows_device_body(c, dev_out, fp64); });
+}
+
+pdr_status pdr_stream(const pdr_ctx *c, void **stream)
+{
+    return abi_guard(nullptr, nullptr, [&] { return pdr_stream_body(c, stream); });
 }
 
 pdr_status pdr_heights(pdr_ctx *c, double *host_out)

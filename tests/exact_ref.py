@@ -334,3 +334,53 @@ def lp_feasible(ex: ExactInstance) -> bool:
             obj = [a - fac * b for a, b in zip(obj, T[leave])]
         basis[leave] = enter
     return -obj[-1] == 0
+
+
+# --------------------------------------------------------------- residual report
+def exact_report(ex: ExactInstance, f) -> dict:
+    """The residual report of a pseudo-flow f (m x K Fractions), in exact arithmetic.
+
+    psi_e = max(0, sum_k f_ek - u_e) (Expression 5); phi_ek = h_ik - h_jk - psi_e
+    (Section 3.3); rho_ek = phi_ek on used entries (f_ek > 0), else max(0, phi_ek);
+    kkt = sum rho^2; z = 1/2 sum psi^2 + 1/2 sum_{i,k} Delta_ik^2 / delta_i
+    (Expression 8); Farkas gap G = sum_k d_k (h_{s_k,k} - h_{t_k,k})
+    - sum_e u_e max(0, max_k (h_ik - h_jk))."""
+    h = ex.heights(f)
+    psi = []
+    for e in range(ex.m):
+        over = sum(f[e], ZERO) - ex.u[e]
+        psi.append(over if over > 0 else ZERO)
+    kkt = ZERO
+    cap_term = ZERO
+    branches = dict(congested=False, used_negative=False, unused_positive=False)
+    for e in range(ex.m):
+        i, j = ex.tail[e], ex.head[e]
+        lmax = ZERO
+        if psi[e] > 0:
+            branches["congested"] = True
+        for k in range(ex.K):
+            diff = h[i][k] - h[j][k]
+            lmax = max(lmax, diff)
+            phi = diff - psi[e]
+            if f[e][k] > 0:
+                rho = phi
+                if phi < 0:
+                    branches["used_negative"] = True
+            else:
+                rho = phi if phi > 0 else ZERO
+                if phi > 0:
+                    branches["unused_positive"] = True
+            kkt += rho * rho
+        cap_term += ex.u[e] * lmax
+    z_psi = sum((p * p for p in psi), ZERO) / 2
+    z_h = ZERO
+    max_delta = ZERO
+    for i in range(ex.n):
+        for k in range(ex.K):
+            delta = h[i][k] * ex.deg[i]
+            z_h += delta * h[i][k] / 2
+            max_delta = max(max_delta, abs(delta))
+    gain = sum((ex.d[k] * (h[ex.s[k]][k] - h[ex.t[k]][k]) for k in range(ex.K)), ZERO)
+    return dict(kkt_sq=kkt, z=z_psi + z_h, z_psi=z_psi, z_h=z_h, max_abs_excess=max_delta,
+                max_congestion=max(psi) if psi else ZERO, farkas_gap=gain - cap_term,
+                branches=branches)

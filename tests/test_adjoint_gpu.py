@@ -56,6 +56,19 @@ def test_congested_instance_gradients():
     assert np.count_nonzero(gu) > 0
 
 
+def test_congested_instance_at_the_adjoint_horizon():
+    """The adjoint configuration's horizon (T = 256, a checkpoint every 16) on
+    the congested x20 instance, against the oracle's forward-mode tangent on
+    every coordinate (m + K = 56)."""
+    base = recipe_grid4_k8()
+    inst = dataclasses.replace(base, d=base.d * 20.0)
+    gu, gd = check(inst, 256, 16)
+    with pdr.Context.from_instance(inst, method=pdr.ESO) as c:
+        c.sweep(256)
+        res = c.residual()
+    assert res["max_congestion"] > 0 and np.count_nonzero(gu) > 0
+
+
 @pytest.mark.parametrize("T,checkpoint", [(0, 0), (1, 0), (37, 16), (37, 1), (37, 64), (40, 7)])
 def test_checkpoint_layouts(T, checkpoint):
     base = recipe_grid4_k8()
@@ -124,7 +137,8 @@ heavy = dataclasses.replace(base, d=base.d * 20.0)
 # is ~1e-3 of the largest gradient times 2h, so its tolerance is 1e-2; the
 # congested instance's differences are clean to 1e-5.
 for name, inst, T, C, tol in (("grid4_k8", base, 256, 16, 1e-2),
-                              ("grid4_k8 x20", heavy, 64, 16, 1e-5)):
+                              ("grid4_k8 x20", heavy, 64, 16, 1e-5),
+                              ("grid4_k8 x20", heavy, 256, 16, 1e-5)):
     for dev in ("cpu", "cuda"):
         u = torch.tensor(inst.u, dtype=torch.float64, device=dev, requires_grad=True)
         d = torch.tensor(inst.d, dtype=torch.float64, device=dev, requires_grad=True)
@@ -136,6 +150,10 @@ for name, inst, T, C, tol in (("grid4_k8", base, 256, 16, 1e-2),
         assert z.item() == z0, (name, dev)
         assert np.array_equal(u.grad.cpu().numpy(), 3.0 * gu0), (name, dev)
         assert np.array_equal(d.grad.cpu().numpy(), 3.0 * gd0), (name, dev)
+        # without a gradient wanted the forward runs the passes only: same z
+        with torch.no_grad():
+            zn = residual_after_sweeps(inst, u.detach(), d.detach(), T, C)
+        assert zn.item() == z0, (name, dev)
     # central differences, h = 1e-6, over every coordinate (m + K = 56)
     h = 1e-6
     scale = max(np.abs(gu0).max(), np.abs(gd0).max())

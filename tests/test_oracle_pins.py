@@ -16,7 +16,7 @@ import pytest
 import oracle
 from conftest import make_instance
 from exact_ref import (ExactInstance, cap_bruteforce, cap_threshold, edge_objective, exact_pdr,
-                       lp_feasible, qp_bruteforce, qp_threshold)
+                       exact_report, lp_feasible, qp_bruteforce, qp_threshold)
 from gen.instance import recipe_grid4_k8, recipe_small
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -266,6 +266,97 @@ def test_agd_objective_change_is_exact_subproblem_difference():
         else:
             assert np.array_equal(out, [float(x) for x in fe])
             assert b == max(1.0 / K, float(beta) / 2)
+
+
+def test_agd_accept_decision_near_convergence():
+    """Reading 12's factored congestion term, pinned where it decides: the two
+    golden cases (tests/golden/agd_accept.txt) make the accept test of
+    Algorithm 3 a small difference of large terms. The oracle's decision and
+    objective change match exact rationals of the same binary64 inputs, and the
+    difference of two squares evaluated in binary64 would decide each case the
+    other way (so the pin discriminates between the two forms)."""
+    rows = {}
+    with open(os.path.join(GOLDEN, "agd_accept.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                p = [x.strip() for x in line.split("|")]
+                rows[p[0]] = (float.fromhex(p[1]), float.fromhex(p[2]), float.fromhex(p[3]), p[4])
+    assert set(rows) == {"reject", "accept"}
+    u = 8.0
+    for name, (hi, f, beta, decision) in rows.items():
+        exact = (edge_objective(Fr(f), [max(-Fr(f), Fr(beta) * (Fr(hi) - (Fr(f) - Fr(u))))],
+                                [Fr(hi)], [Fr(0)], Fr(u))
+                 - edge_objective(Fr(f), [Fr(0)], [Fr(hi)], [Fr(0)], Fr(u)))
+        assert (exact <= 0) == (decision == "accept"), name
+        out, b, acc, dz = oracle.agd_edge([hi], [0.0], [f], u, 1, beta)
+        assert acc == (decision == "accept"), name
+        assert dz == pytest.approx(float(exact), rel=1e-6, abs=1e-12), name
+        # the unfactored form, in binary64
+        psi = f - u
+        df = max(-f, beta * (hi - psi))
+        after = f + df - u
+        naive = 0.5 * (after * after - psi * psi) + df * (df - hi)
+        assert (naive <= 0) != (decision == "accept"), name
+    hi, f, beta, _ = rows["reject"]
+    assert float(exact_ref_dz := (edge_objective(Fr(f), [Fr(1, 8)], [Fr(hi)], [Fr(0)], Fr(u))
+                                  - edge_objective(Fr(f), [Fr(0)], [Fr(hi)], [Fr(0)], Fr(u)))) \
+        == 2.0 ** -7, exact_ref_dz
+
+
+# ------------------------------------------------------------------ residual report
+def _read_report_golden():
+    rows = {}
+    with open(os.path.join(GOLDEN, "two_vertex_report.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                p = [x.strip() for x in line.split("|")]
+                rows[p[0]] = [Fr(x) for x in p[1:]]
+    return rows
+
+
+def test_report_hand_derived_two_vertex():
+    """The residual report (kkt of Section 3.3's stable-flow conditions, z,
+    max |Delta|, max psi, Farkas gap) at hand-derived non-stationary pseudo-flows
+    of the two-vertex instance (tests/golden/two_vertex_report.txt): unused arcs
+    with phi > 0 and phi < 0, congested arcs, used arcs with phi < 0."""
+    inst = two_vertex(10.0, 8.0)
+    rows = _read_report_golden()
+    assert set(rows) == {"f0", "f3", "f4", "r1", "r2"}
+    for name, (a, b, kkt, z, zpsi, maxd, maxpsi, gap) in rows.items():
+        f = np.array([[float(a)], [float(b)]])
+        rep = oracle.report(inst, f)
+        for key, want in (("kkt_sq", kkt), ("z", z), ("z_psi", zpsi), ("max_abs_excess", maxd),
+                          ("max_congestion", maxpsi), ("farkas_gap", gap)):
+            assert rep[key] == pytest.approx(float(want), rel=1e-14, abs=1e-14), (name, key)
+        ex = exact_report(ExactInstance.from_instance(inst), [[Fr(a)], [Fr(b)]])
+        assert ex["kkt_sq"] == kkt and ex["z"] == z and ex["farkas_gap"] == gap, name
+    # the verdict: G > 0 certifies infeasibility already at f3 (Theorem 2's direction)
+    assert oracle.report(inst, np.array([[8.5], [0.0]]))["verdict"] == "infeasible"
+
+
+@pytest.mark.parametrize("method", [oracle.ESO, oracle.AGD, oracle.GDM])
+@pytest.mark.parametrize("T", [2, 3, 11])
+def test_report_matches_exact_rationals_at_non_stationary_iterates(grid4, method, T):
+    """kkt_sq and the rest of the report at congested iterates away from a
+    stationary point: the FP64 oracle's report of its own flows after T passes
+    equals the exact-rational report of the same flows (independent code), on
+    iterates where every branch of the kkt residual occurs (congested arcs,
+    used entries with phi < 0, unused entries with phi > 0)."""
+    import dataclasses
+    inst = dataclasses.replace(grid4, d=grid4.d * 20.0)  # congested
+    st, _ = oracle.run(inst, method, T)
+    rep = oracle.report(inst, st.f)
+    ex = ExactInstance.from_instance(inst)
+    fx = [[Fr(float(x)) for x in row] for row in st.f]
+    want = exact_report(ex, fx)
+    assert want["branches"] == dict(congested=True, used_negative=True, unused_positive=True)
+    assert want["kkt_sq"] > 0
+    for key in ("kkt_sq", "z", "z_psi", "z_h", "max_abs_excess", "max_congestion"):
+        assert rep[key] == pytest.approx(float(want[key]), rel=1e-12, abs=1e-12), key
+    assert rep["farkas_gap"] == pytest.approx(float(want["farkas_gap"]),
+                                              abs=1e-12 * float(np.max(inst.u)) * inst.m)
 
 
 # ------------------------------------------------------------------ P4: exact sweeps
