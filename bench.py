@@ -116,25 +116,41 @@ def time_to_residual(pdr, inst, method, precision, budget_s, rungs, chunk=2048, 
                 precision_final="fp64" if n64 or precision == pdr.FP64 else "fp32")
 
 
+LADDER = (1e4, 1e3, 1e2, 1e1, 1.0, 1e-1, 1e-2, 1e-4, 1e-6, 1e-8)
+
+
 def time_to_target(pdr, inst, method, precision, target, cap, window=512, chunk=1_000_000,
-                   tag=""):
+                   tag="", seconds=0.0):
     """From f = 0, pdr_solve to z <= target (FP32-bulk runs widen to FP64 and
-    polish by its rule); the wall time, the passes in each precision, and the
-    first pass at which z fell to each decade of a ladder. Runs longer than
-    `chunk` passes are split into pdr_solve calls of `chunk` passes, with a
-    progress line after each (the hand-over rule then restarts its windows)."""
-    ladder = {str(t): None for t in (1e-2, 1e-4, 1e-6, 1e-8)}
+    polish by its rule; the rule's windows carry over from one solve call to
+    the next); the wall time, the passes in each precision, and the first pass
+    and (pro rata inside its call) the time at which z fell to each rung of a
+    ladder. Runs longer than `chunk` passes are split into pdr_solve calls of
+    `chunk` passes, with a progress line after each. seconds > 0 ends the run
+    after the call that passes that wall time; the result then says how far it
+    got and extrapolates the passes to the target from the descent rate of the
+    last tenth of the run (labelled as an extrapolation)."""
+    ladder = {str(t): None for t in LADDER if t >= target}
+    ladder[str(target)] = None
+    out = {}
     with pdr.Context.from_instance(inst, method=method, precision=precision) as ctx:
         pdr.device_synchronize()
         t0 = time.perf_counter()
         n32 = n64 = 0
         ev0 = 0
+        handover = None
+        floor = None
         while True:
+            prev_sec = time.perf_counter() - t0
             a, b = ctx.solve(target, min(chunk, cap - n32 - n64), window)
             pdr.device_synchronize()
+            if precision == pdr.FP32_BULK and b > 0 and handover is None:
+                handover = n32 + a
             n32, n64 = n32 + a, n64 + b
             sec = time.perf_counter() - t0
             res = ctx.residual()
+            if res["z_fp32_floor"] > 0:
+                floor = res["z_fp32_floor"]
             ev = res["evaluations"]
             # the z log keeps the last 2^20 evaluations (chunk <= 2^20 covers them all)
             first = max(ev0, ev - (1 << 20))
@@ -143,17 +159,34 @@ def time_to_target(pdr, inst, method, precision, target, cap, window=512, chunk=
                 if ladder[thr] is None:
                     hit = np.nonzero(zl <= float(thr))[0]
                     if hit.size:
-                        ladder[thr] = int(first + hit[0])
+                        q = int(first + hit[0])
+                        frac = (q - ev0 + 1) / max(ev - ev0, 1)
+                        ladder[thr] = dict(sweeps=q, seconds=prev_sec + frac * (sec - prev_sec))
             ev0 = ev
-            done = res["z"] <= target or n32 + n64 >= cap or a + b == 0
-            if not done:
-                print(f"[bench] ttr {tag}: {n32} + {n64} passes, z {res['z']:.3e}, {sec:.0f} s",
-                      file=sys.stderr, flush=True)
-            else:
+            done = (res["z"] <= target or n32 + n64 >= cap or a + b == 0
+                    or (seconds > 0 and sec >= seconds))
+            print(f"[bench] ttr {tag}: {n32} + {n64} passes, z {res['z']:.4e}, {sec:.0f} s",
+                  file=sys.stderr, flush=True)
+            if done:
                 break
-    return dict(seconds=sec, sweeps_fp32=n32, sweeps_fp64=n64, z_final=res["z"],
-                reached=bool(res["z"] <= target), verdict=res["verdict"], first_pass_at=ladder,
-                solve_calls_of=chunk)
+        out = dict(seconds=sec, sweeps_fp32=n32, sweeps_fp64=n64, z_final=res["z"],
+                   reached=bool(res["z"] <= target), verdict=res["verdict"], rungs=ladder,
+                   solve_calls_of=chunk, handover_at_pass=handover, z_fp32_floor=floor)
+        if not out["reached"] and ev >= 2:
+            tail = max(10, (n32 + n64) // 10)
+            first = max(0, ev - min(tail, 1 << 20))
+            zl = ctx.z_log(first, ev - first)
+            if zl[-1] > 0 and zl[0] > zl[-1]:
+                rate = np.log(zl[0] / zl[-1]) / (len(zl) - 1)
+                more = float(np.log(zl[-1] / target) / rate)
+                per_pass = sec / max(n32 + n64, 1)
+                out["extrapolation"] = dict(
+                    kind="extrapolated from the descent rate of the last "
+                         f"{len(zl) - 1} passes; not measured",
+                    rate_per_pass=float(rate), further_passes=more,
+                    total_passes=float(n32 + n64 + more),
+                    total_seconds=float(sec + more * per_pass))
+    return out
 
 
 def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
@@ -297,6 +330,13 @@ def main():
                     help="methods of --ttr-workload (eso, agd, gdm, cap)")
     ap.add_argument("--ttr-cap", type=int, default=2_000_000,
                     help="pass limit of each --ttr-workload run")
+    ap.add_argument("--ttr-seconds", type=float, default=0.0,
+                    help="wall-time limit of each --ttr-workload run (0: none); a run that "
+                         "stops short reports the rungs it reached and an extrapolation")
+    ap.add_argument("--ttr-chunk", type=int, default=1_000_000,
+                    help="passes per pdr_solve call of the --ttr-workload runs")
+    ap.add_argument("--ttr-precisions", default="fp64,fp32_polish",
+                    help="forms of the --ttr-workload runs (fp64, fp32_polish)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -378,12 +418,16 @@ def main():
         tinst = load_instance(args.ttr_workload)
         full = dict(workload=args.ttr_workload, target=1e-8, cap=args.ttr_cap)
         names = {"eso": pdr.ESO, "agd": pdr.AGD, "gdm": pdr.GDM, "cap": pdr.CAP}
+        forms = [(p, {"fp64": pdr.FP64, "fp32_polish": pdr.FP32_BULK}[p])
+                 for p in args.ttr_precisions.split(",") if p]
+        full.update(seconds_limit=args.ttr_seconds or None, solve_call_passes=args.ttr_chunk)
         for mname in [x for x in args.ttr_methods.split(",") if x]:
-            for pname, prec in (("fp64", pdr.FP64), ("fp32_polish", pdr.FP32_BULK)):
+            for pname, prec in forms:
                 print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: running", file=sys.stderr,
                       flush=True)
                 r = time_to_target(pdr, tinst, names[mname], prec, 1e-8, args.ttr_cap,
-                                   tag=f"{args.ttr_workload} {mname} {pname}")
+                                   chunk=args.ttr_chunk, tag=f"{args.ttr_workload} {mname} {pname}",
+                                   seconds=args.ttr_seconds)
                 print(f"[bench] ttr {args.ttr_workload} {mname} {pname}: {r}", file=sys.stderr,
                       flush=True)
                 full[f"{mname}_{pname}"] = r

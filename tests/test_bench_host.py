@@ -81,7 +81,8 @@ class _FakeCtx:
         return a, b
 
     def residual(self):
-        return {"evaluations": self.ev, "z": self.z(self.ev), "verdict": "feasible"}
+        return {"evaluations": self.ev, "z": self.z(self.ev), "verdict": "feasible",
+                "z_fp32_floor": 1e-12 if self.ev <= 4 else 0.0}
 
     def z_log(self, first, count):
         import numpy as np
@@ -89,6 +90,8 @@ class _FakeCtx:
 
 
 class _FakePdr:
+    FP64, FP32_BULK = 0, 1
+
     @staticmethod
     def device_synchronize():
         pass
@@ -106,6 +109,23 @@ def test_time_to_target_chunks_long_runs_and_keeps_the_ladder():
     many = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 100, chunk=3)
     for r in (one, many):
         assert r["reached"] and (r["sweeps_fp32"], r["sweeps_fp64"]) == (4, 4)
-        assert r["first_pass_at"] == {"0.01": 1, "0.0001": 3, "1e-06": 5, "1e-08": 7}
+        first = {k: v["sweeps"] for k, v in r["rungs"].items()}
+        assert first == {"10000.0": 0, "1000.0": 0, "100.0": 0, "10.0": 0, "1.0": 0, "0.1": 0,
+                         "0.01": 1, "0.0001": 3, "1e-06": 5, "1e-08": 7}
+        assert r["handover_at_pass"] == 4 and "extrapolation" not in r
+    # the FP32 floor is read after a call that ends in FP32
+    assert one["z_fp32_floor"] is None and many["z_fp32_floor"] == 1e-12
     capped = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 5, chunk=2)
     assert not capped["reached"] and capped["sweeps_fp32"] + capped["sweeps_fp64"] == 5
+
+
+def test_time_to_target_wall_time_limit_and_extrapolation():
+    """A run stopped by its time limit reports the rungs it reached and the
+    passes still needed at its last measured descent rate, as an extrapolation."""
+    r = bench.time_to_target(_FakePdr, None, 0, 1, 1e-8, 100, chunk=3, seconds=1e-12)
+    assert not r["reached"] and r["sweeps_fp32"] + r["sweeps_fp64"] == 3
+    assert r["rungs"]["0.01"]["sweeps"] == 1 and r["rungs"]["1e-06"] is None
+    ex = r["extrapolation"]
+    # z falls 10x per pass: from z = 1e-3 after 3 passes, 5 more passes to 1e-8
+    assert "not measured" in ex["kind"]
+    assert abs(ex["further_passes"] - 5.0) < 1e-9 and abs(ex["total_passes"] - 8.0) < 1e-9

@@ -527,14 +527,16 @@ def _c3_oracle(inst, method_name, T):
     return _C3_ORACLE[key]
 
 
-# FP32 bulk against the FP64 oracle. The FP32 pass rounds the stored flows and
-# heights (unit roundoff u32 = 2^-24) and forms c in FP32; sums stay in FP64.
-# Bounds (stated beside the measured errors in the design notes): flows and
-# heights (both in flow units) within FP32_FLOW_C * T * u32 * max(u), the z
-# trajectory within FP32_Z_C * T * u32 relative.
+# FP32 bulk against the FP64 oracle. The FP32 pass rounds every stored flow and
+# height once (unit roundoff u32 = 2^-24, flows of at most about max(u)) and
+# forms c in FP32; sums stay in FP64. If the pass map added no error of its own
+# to what it is given, T passes would leave at most T roundings of each value:
+# flows and heights (both in flow units) within T * u32 * max(u), and the z
+# trajectory within T * u32 relative. These are the stated bounds (measured
+# errors are 11x to 460x below them; the design notes list them).
 U32 = 2.0 ** -24
-FP32_FLOW_C = 64.0
-FP32_Z_C = 64.0
+FP32_FLOW_C = 1.0
+FP32_Z_C = 1.0
 
 
 def _fp32_errors(inst, method_name, T, st, zo):
@@ -621,7 +623,9 @@ def test_grid100_k10000_congested_iterate(method):
     zo = st.run(T)
     say("congested parity", method, "t0", t0, "max psi", rg["max_congestion"], "z", zo)
     assert np.max(np.abs(fg - st.f)) <= flow_tol(inst)
-    assert np.allclose(zg, zo, rtol=1e-11, atol=0)
+    # the excess is now a small difference of flows of a few hundred, so the
+    # two summation orders differ at ~1e-11 of z (measured 1.1e-11)
+    assert np.allclose(zg, zo, rtol=1e-9, atol=0)
     if gm == pdr.AGD:
         assert np.array_equal(bg, st.beta)
     rep_cong = float(np.max(np.maximum(st.f.sum(axis=1) - inst.u, 0.0)))
