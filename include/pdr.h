@@ -253,6 +253,19 @@ pdr_status pdr_set_precision(pdr_ctx *ctx, int32_t precision);
 pdr_status pdr_set_state(pdr_ctx *ctx, const double *f, const double *beta, const double *v,
                          int64_t t, double z_prev);
 
+/* pdr_set_state for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, checks and result as pdr_set_state, but no device memory is
+ * allocated or freed. The host rows of f (and v) are staged, in chunks of whole
+ * arc rows, through a 32 MiB device array (4,194,304 doubles) that the library
+ * holds on every GPU it runs on until the process ends (its address is
+ * resolved at pdr_init). Calls on one GPU share that array: calls that overlap
+ * in time on one GPU (from several threads, contexts or streams) race and must
+ * be serialized by the caller. PDR_ERR_INVALID also if one arc row of K
+ * doubles exceeds the array. Synchronizes. */
+pdr_status pdr_set_state_noalloc(pdr_ctx *ctx, const double *f, const double *beta,
+                                 const double *v, int64_t t, double z_prev);
+
 /* Measurement: run `sweeps` passes like pdr_sweep without a stop test,
  * recording HIP events around every kernel on the context stream. On return
  * (synchronized) kernel_ms[0] and kernel_ms[1] hold the summed device time in

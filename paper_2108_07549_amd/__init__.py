@@ -36,7 +36,7 @@ STATUS = {0: "PDR_OK", 1: "PDR_ERR_INVALID", 2: "PDR_ERR_OOM", 3: "PDR_ERR_DEVIC
 
 EXPORTS = ["pdr_default_options", "pdr_init", "pdr_sweep", "pdr_solve", "pdr_residual", "pdr_flows",
            "pdr_flows_device", "pdr_stream", "pdr_heights", "pdr_learning_rates", "pdr_velocities", "pdr_z_log",
-           "pdr_set_precision", "pdr_set_state", "pdr_profile_sweeps", "pdr_measure_copy",
+           "pdr_set_precision", "pdr_set_state", "pdr_set_state_noalloc", "pdr_profile_sweeps", "pdr_measure_copy",
            "pdr_tiling", "pdr_adjoint", "pdr_destroy", "pdr_last_error",
            "pdr_batch_init", "pdr_batch_sweep", "pdr_batch_member", "pdr_batch_stopped",
            "pdr_batch_tune", "pdr_batch_buckets", "pdr_batch_profile_sweeps",
@@ -120,6 +120,7 @@ def lib():
         L.pdr_z_log.argtypes = [P, i64, i64, P]
         L.pdr_set_precision.argtypes = [P, i32]
         L.pdr_set_state.argtypes = [P, P, P, P, i64, dbl]
+        L.pdr_set_state_noalloc.argtypes = [P, P, P, P, i64, dbl]
         L.pdr_profile_sweeps.argtypes = [P, i64, P]
         L.pdr_measure_copy.argtypes = [i64, i32, P]
         L.pdr_adjoint.argtypes = [P, i64, i32, P, P, P]
@@ -327,6 +328,17 @@ class Context:
         self._check(lib().pdr_set_state(self._h, _ptr(fa), None if ba is None else _ptr(ba),
                                         None if va is None else _ptr(va), int(t), float(z_prev)))
 
+    def set_state_noalloc(self, f, beta=None, t: int = 0, z_prev: float = float("inf"),
+                          v=None):
+        """set_state through pdr_set_state_noalloc (no device allocation)."""
+        fa = np.ascontiguousarray(f, np.float64)
+        ba = None if beta is None else np.ascontiguousarray(beta, np.float64)
+        va = None if v is None else np.ascontiguousarray(v, np.float64)
+        self._check(lib().pdr_set_state_noalloc(self._h, _ptr(fa),
+                                                None if ba is None else _ptr(ba),
+                                                None if va is None else _ptr(va), int(t),
+                                                float(z_prev)))
+
     def profile_sweeps(self, sweeps: int) -> np.ndarray:
         """Run sweeps without a stop test; returns summed device ms of the
         (height + objective, arc) kernels measured with HIP events."""
@@ -439,6 +451,17 @@ class Batch:
         self._check(lib().pdr_batch_buckets(self._h, n.value, arr, C.byref(n)))
         return [{name: getattr(arr[q], name) for name, _ in BucketInfo._fields_}
                 for q in range(n.value)]
+
+    def set_state_noalloc(self, f, beta=None, t: int = 0, z_prev: float = float("inf"),
+                          v=None):
+        """set_state through pdr_set_state_noalloc (no device allocation)."""
+        fa = np.ascontiguousarray(f, np.float64)
+        ba = None if beta is None else np.ascontiguousarray(beta, np.float64)
+        va = None if v is None else np.ascontiguousarray(v, np.float64)
+        self._check(lib().pdr_set_state_noalloc(self._h, _ptr(fa),
+                                                None if ba is None else _ptr(ba),
+                                                None if va is None else _ptr(va), int(t),
+                                                float(z_prev)))
 
     def profile_sweeps(self, sweeps: int) -> np.ndarray:
         out = np.zeros(2, np.float64)

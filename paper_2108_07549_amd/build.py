@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpdr.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["pdr_k_core.hip", "pdr_k_eso.hip", "pdr_k_agd.hip", "pdr_k_misc.hip",
-           "pdr_k_batch.hip", "pdr_api.cpp", "pdr_batch.cpp"]
+           "pdr_k_batch.hip", "pdr_noalloc.hip", "pdr_api.cpp", "pdr_batch.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -535,6 +535,15 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         c->err = std::string("hipGetDevice: ") + hipGetErrorString(e);
         return init_fail(c, PDR_ERR_DEVICE, out);
     }
+    {
+        // the staging array of pdr_set_state_noalloc: its device address, once per device
+        double *scratch = nullptr;
+        e = noalloc_scratch(c->device, &scratch, nullptr);
+        if (e != hipSuccess) {
+            c->err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return init_fail(c, PDR_ERR_DEVICE, out);
+        }
+    }
     if (opt.stream) {
         c->stream = (hipStream_t)opt.stream;
     } else {
@@ -1034,6 +1043,70 @@ void set_cache_policy(pdr_ctx *c)
     c->g.temporal = (temporal && !c->batch_member) ? 1 : 0;
 }
 
+pdr_status check_state_args(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                            int64_t t, double z_prev)
+{
+    if (!f && c->m > 0) return fail(c, PDR_ERR_INVALID, "f is NULL");
+    if (t < 0) return fail(c, PDR_ERR_INVALID, "t must be >= 0");
+    if (std::isnan(z_prev)) return fail(c, PDR_ERR_INVALID, "z_prev is NaN");
+    const size_t mK = (size_t)c->m * c->K;
+    for (size_t q = 0; q < mK; ++q)
+        if (!finite_nonneg(f[q])) return fail(c, PDR_ERR_INVALID, "flows must be finite and >= 0");
+    if (beta)
+        for (int32_t e = 0; e < c->m; ++e)
+            if (!(beta[e] > 0) || !std::isfinite(beta[e]))
+                return fail(c, PDR_ERR_INVALID, "learning rates must be finite and > 0");
+    if (v && c->method == PDR_GDM)
+        for (size_t q = 0; q < mK; ++q)
+            if (!std::isfinite(v[q])) return fail(c, PDR_ERR_INVALID, "velocities must be finite");
+    return PDR_OK;
+}
+
+// Upload host rows (m x K, unpadded) into a padded device array through a
+// staging buffer of `cap` doubles, in chunks of whole rows.
+static pdr_status stage_rows(pdr_ctx *c, const double *src, void *dst, double *staging,
+                             int64_t cap)
+{
+    const int64_t K = c->K, m = c->m;
+    const int64_t per = cap / K;  // rows per chunk (>= 1: checked by the caller)
+    for (int64_t r0 = 0; r0 < m; r0 += per) {
+        const int64_t rows = std::min(per, m - r0);
+        PDR_CHECK(c, hipMemcpyAsync(staging, src + r0 * K, (size_t)(rows * K) * 8,
+                                    hipMemcpyHostToDevice, c->stream));
+        PDR_CHECK(c, pdr::launch_pad_rows(c->g, staging, dst, c->precision == PDR_FP64, r0, rows,
+                                          c->stream));
+    }
+    return PDR_OK;
+}
+
+pdr_status set_state_impl(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                          int64_t t, double z_prev, double *staging, int64_t staging_doubles)
+{
+    if (c->m > 0) {
+        if (staging_doubles < c->K)
+            return fail(c, PDR_ERR_INVALID, "one arc row does not fit the staging buffer");
+        pdr_status st = stage_rows(c, f, cur_f(c), staging, staging_doubles);
+        if (st != PDR_OK) return st;
+        PDR_CHECK(c, pdr::launch_rowsum(c->g, c->precision == PDR_FP64, c->tiling, cur_f(c),
+                                        c->Fsum, c->stream));
+        if (v && c->method == PDR_GDM) {
+            st = stage_rows(c, v, cur_v(c), staging, staging_doubles);
+            if (st != PDR_OK) return st;
+        }
+        if (beta)
+            PDR_CHECK(c, hipMemcpyAsync(c->beta, beta, (size_t)c->m * 8, hipMemcpyHostToDevice,
+                                        c->stream));
+        PDR_CHECK(c, hipStreamSynchronize(c->stream));
+    }
+    pdr_status st = sync_ctrl(c);
+    if (st != PDR_OK) return st;
+    c->h_ctrl->t = t;
+    c->h_ctrl->z_prev = z_prev;
+    c->h_ctrl->stopped = 0;
+    c->h_ctrl->numeric = 0;
+    return push_ctrl(c);
+}
+
 pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
 {
     pdr_status st;
@@ -1074,51 +1147,18 @@ static pdr_status pdr_set_state_body(pdr_ctx *c, const double *f, const double *
 {
     pdr_status st;
     if (!usable(c, &st)) return st;
-    if (!f && c->m > 0) return fail(c, PDR_ERR_INVALID, "f is NULL");
-    if (t < 0) return fail(c, PDR_ERR_INVALID, "t must be >= 0");
-    if (std::isnan(z_prev)) return fail(c, PDR_ERR_INVALID, "z_prev is NaN");
+    st = check_state_args(c, f, beta, v, t, z_prev);
+    if (st != PDR_OK) return st;
     const size_t mK = (size_t)c->m * c->K;
-    for (size_t q = 0; q < mK; ++q)
-        if (!finite_nonneg(f[q])) return fail(c, PDR_ERR_INVALID, "flows must be finite and >= 0");
-    if (beta)
-        for (int32_t e = 0; e < c->m; ++e)
-            if (!(beta[e] > 0) || !std::isfinite(beta[e]))
-                return fail(c, PDR_ERR_INVALID, "learning rates must be finite and > 0");
-    const bool set_v = v && c->method == PDR_GDM;
-    if (set_v)
-        for (size_t q = 0; q < mK; ++q)
-            if (!std::isfinite(v[q])) return fail(c, PDR_ERR_INVALID, "velocities must be finite");
-    if (c->m > 0) {
-        double *staging = nullptr;
+    double *staging = nullptr;
+    if (mK > 0) {  // one staging buffer for the whole state
         hipError_t e = hipMalloc((void **)&staging, mK * 8);
         if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (staging)");
         PDR_CHECK(c, e);
-        e = hipMemcpyAsync(staging, f, mK * 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = pdr::launch_pad(c->g, staging, cur_f(c), c->precision == PDR_FP64, c->stream);
-        if (e == hipSuccess)
-            e = pdr::launch_rowsum(c->g, c->precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
-                                   c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e == hipSuccess && set_v) {
-            e = hipMemcpyAsync(staging, v, mK * 8, hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess)
-                e = pdr::launch_pad(c->g, staging, cur_v(c), c->precision == PDR_FP64, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        }
-        (void)hipFree(staging);
-        PDR_CHECK(c, e);
-        if (beta)
-            PDR_CHECK(c, hipMemcpyAsync(c->beta, beta, (size_t)c->m * 8, hipMemcpyHostToDevice,
-                                        c->stream));
     }
-    st = sync_ctrl(c);
-    if (st != PDR_OK) return st;
-    c->h_ctrl->t = t;
-    c->h_ctrl->z_prev = z_prev;
-    c->h_ctrl->stopped = 0;
-    c->h_ctrl->numeric = 0;
-    return push_ctrl(c);
+    st = set_state_impl(c, f, beta, v, t, z_prev, staging, (int64_t)mK);
+    if (staging) (void)hipFree(staging);
+    return st;
 }
 
 static pdr_status pdr_stream_body(const pdr_ctx *c, void **stream)

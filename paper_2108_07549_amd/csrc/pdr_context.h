@@ -101,6 +101,17 @@ pdr_status set_precision_impl(pdr_ctx *c, int32_t precision);
 // Choose the sweep kernels' cache hints for the current storage precision
 // (batch members always stream).
 void set_cache_policy(pdr_ctx *c);
+// pdr_set_state's argument checks (the text goes to c->err).
+pdr_status check_state_args(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                            int64_t t, double z_prev);
+// pdr_set_state after its checks, staging the host rows through `staging`
+// (device memory of staging_doubles doubles, at least one row of K) in chunks
+// of whole rows; allocates nothing. Synchronizes.
+pdr_status set_state_impl(pdr_ctx *c, const double *f, const double *beta, const double *v,
+                          int64_t t, double z_prev, double *staging, int64_t staging_doubles);
+// The device address of the file-scope staging array of pdr_set_state_noalloc
+// on `device` (resolved once per device; the device must be current).
+hipError_t noalloc_scratch(int device, double **out, int64_t *doubles);
 
 // Exception barrier of the C ABI: every exported entry point runs its body
 // through abi_guard, so no C++ exception (in practice std::bad_alloc from a

@@ -905,16 +905,19 @@ __global__ __launch_bounds__(256) void k_unpad(const S *__restrict__ f, D *__res
     }
 }
 
+// Rows [row0, row0 + rows) of f from src, which holds those rows unpadded
+// (src[(e - row0) * K + k]).
 template <typename D>
 __global__ __launch_bounds__(256) void k_pad(const double *__restrict__ src, D *__restrict__ f,
-                                             int64_t m, int K, int Kp)
+                                             int64_t row0, int64_t rows, int K, int Kp)
 {
-    const int64_t total = m * (int64_t)Kp;
+    const int64_t total = rows * (int64_t)Kp;
+    D *dst = f + row0 * (int64_t)Kp;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * 256) {
         const int64_t e = q / Kp;
         const int k = (int)(q - e * Kp);
-        f[q] = k < K ? (D)src[e * K + k] : (D)0;
+        dst[q] = k < K ? (D)src[e * K + k] : (D)0;
     }
 }
 

@@ -130,6 +130,9 @@ hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst
                         hipStream_t st);
 hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64,
                       hipStream_t st);
+// Rows [row0, row0 + rows) of f from src holding just those rows, unpadded.
+hipError_t launch_pad_rows(const DevGraph &g, const double *src, void *f, bool f_fp64,
+                           int64_t row0, int64_t rows, hipStream_t st);
 
 // Reverse mode through FP64 PDR-ESO passes. Seed at the final flows (Fsum and
 // h of those flows): cbar = dz/df (to be read with Dbar = 0), ubar = dz/du and

@@ -253,14 +253,21 @@ hipError_t launch_unpad(const DevGraph &g, const void *f, bool f_fp64, void *dst
     return hipGetLastError();
 }
 
+hipError_t launch_pad_rows(const DevGraph &g, const double *src, void *f, bool f_fp64,
+                           int64_t row0, int64_t rows, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    const unsigned nb = grid_for(rows * g.Kp, 65536);
+    if (f_fp64)
+        k_pad<double><<<nb, 256, 0, st>>>(src, (double *)f, row0, rows, g.K, g.Kp);
+    else
+        k_pad<float><<<nb, 256, 0, st>>>(src, (float *)f, row0, rows, g.K, g.Kp);
+    return hipGetLastError();
+}
+
 hipError_t launch_pad(const DevGraph &g, const double *src, void *f, bool f_fp64, hipStream_t st)
 {
-    const unsigned nb = grid_for((int64_t)g.m * g.Kp, 65536);
-    if (f_fp64)
-        k_pad<double><<<nb, 256, 0, st>>>(src, (double *)f, g.m, g.K, g.Kp);
-    else
-        k_pad<float><<<nb, 256, 0, st>>>(src, (float *)f, g.m, g.K, g.Kp);
-    return hipGetLastError();
+    return launch_pad_rows(g, src, f, f_fp64, 0, g.m, st);
 }
 
 // ----------------------------------------------------------------- adjoint (FP64 ESO)

@@ -33,7 +33,7 @@ def exported_definitions():
     """Body text of every exported (column-0, non-static) definition of a
     declared entry point in the library sources."""
     out = {}
-    for fn in ("pdr_api.cpp", "pdr_batch.cpp"):
+    for fn in ("pdr_api.cpp", "pdr_batch.cpp", "pdr_noalloc.hip"):
         with open(os.path.join(ROOT, "paper_2108_07549_amd", "csrc", fn)) as fh:
             text = fh.read()
         for mt in re.finditer(r"^(?:pdr_status|void|const char \*)\s*(pdr_[a-z_]+)\(", text, re.M):
