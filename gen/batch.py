@@ -5,16 +5,17 @@ family (random geometric 4-NN graphs, Section 7.1) with uneven sizes:
 n ~ U{100..5000}, K ~ U{16..2000} (at most n(n-1)/2), capacities U{100..1000},
 integer demands U{1..20} scaled to a per-instance load factor LF ~ U[0.7, 1.1].
 
-Scaling uses a congestion bracket [mu_lo, mu_hi] of the unscaled demands from
-two Frank-Wolfe steps of ``gen.loadfactor.congestion_bracket_fw`` (an explicit
-routing gives mu_hi, dual arc lengths give mu_lo; no LP). The bracket is loose,
-so an instance with LF > 1 is usually uncertified, and one with LF <= 1 is
-certified feasible but may be lightly loaded. With alpha = LF / mu_hi the scaled instance's
-minimum congestion lies in [LF mu_lo / mu_hi, LF]: it is certified feasible if
-LF <= 1, certified infeasible if LF mu_lo / mu_hi > 1, and uncertified
-otherwise. The brackets are computed once by ``python -m gen.batch`` and kept in
-``gen/batch_loadfactor.json``; this module holds no part of the PDR method's
-arithmetic.
+Scaling uses a certified bracket mu_lo <= mu* <= mu_hi of the minimum
+congestion mu* of the unscaled demands (mu* = 1 / maximum concurrent flow),
+from path column generation on HiGHS (``gen.loadfactor.congestion_bracket``:
+an explicit routing gives mu_hi, the master's dual arc lengths give mu_lo by
+weak duality). A member with LF <= 1 is scaled by alpha = LF / mu_hi, so its
+minimum congestion alpha mu* <= LF <= 1: certified feasible, true load factor
+in [LF mu_lo / mu_hi, LF]. A member with LF > 1 is scaled by alpha = LF / mu_lo,
+so alpha mu* >= LF > 1: certified infeasible, true load factor in
+[LF, LF mu_hi / mu_lo]. The brackets are computed once by
+``python -m gen.batch`` and kept in ``gen/batch_loadfactor.json``; this module
+holds no part of the PDR method's arithmetic.
 
 Instance b of batch seed S uses the sub-seed 100000 + 1000 S + b for its graph,
 OD pairs, capacities and demands (the streams of ``gen.instance.stream``), so
@@ -80,34 +81,53 @@ def recipe_batch(B: int = 256, seed: int = 4, scale: bool = True):
                 raise KeyError(f"batch instance {key} has no bracket in {_FILE}; "
                                f"run python -m gen.batch {B} {seed}")
             br = tab[key]
-            inst = inst.demand_scaled(float(lf[b]) / br["mu_hi"])
-            lo = float(lf[b]) * br["mu_lo"] / br["mu_hi"]
-            inst.meta.update(load_factor=float(lf[b]), lf_bracket=[lo, float(lf[b])],
-                             certified=("feasible" if lf[b] <= 1.0 else
-                                        "infeasible" if lo > 1.0 else "uncertified"))
+            target = float(lf[b])
+            ratio = br["mu_hi"] / br["mu_lo"] if br["mu_lo"] > 0 else float("inf")
+            if target <= 1.0:
+                inst = inst.demand_scaled(target / br["mu_hi"])
+                bracket, label = [target / ratio, target], "feasible"
+            elif br["mu_lo"] > 0:
+                inst = inst.demand_scaled(target / br["mu_lo"])
+                bracket, label = [target, target * ratio], "infeasible"
+            else:  # no lower bound: scaled as a feasible target, label unknown
+                inst = inst.demand_scaled(target / br["mu_hi"])
+                bracket, label = [0.0, target], "uncertified"
+            inst.meta.update(load_factor=target, lf_bracket=bracket, certified=label,
+                             mu_hi=br["mu_hi"], mu_lo=br["mu_lo"])
         out.append(inst)
     return out
 
 
+def _bracket(args):
+    from .loadfactor import congestion_bracket
+    seed, b, n, K = args
+    inst = unscaled_instance(seed, b, n, K)
+    br = congestion_bracket(inst, gap=1e-4, max_iter=60, time_limit=1800.0)
+    return f"{seed}:{b}", dict(mu_hi=br["mu_hi"], mu_lo=br["mu_lo"], iters=br["iters"],
+                               method="column generation"), n, K, br["seconds"]
+
+
 def main(argv):
-    from .loadfactor import congestion_bracket_fw
+    """python -m gen.batch [B] [seed] [workers]: the bracket of every member that
+    has no column-generation bracket yet, written to gen/batch_loadfactor.json."""
+    from multiprocessing import Pool
     B = int(argv[0]) if argv else 256
     seed = int(argv[1]) if len(argv) > 1 else 4
-    iters = int(argv[2]) if len(argv) > 2 else 2
+    workers = int(argv[2]) if len(argv) > 2 else 4
     n, K, _ = batch_shapes(B, seed)
     tab = _table()
+    todo = [(seed, b, int(n[b]), int(K[b])) for b in range(B)
+            if tab.get(f"{seed}:{b}", {}).get("method") != "column generation"]
+    todo.sort(key=lambda a: -a[2] * a[3])  # largest first
     t0 = time.time()
-    for b in range(B):
-        key = f"{seed}:{b}"
-        if key in tab:
-            continue
-        inst = unscaled_instance(seed, b, n[b], K[b])
-        br = congestion_bracket_fw(inst, iters=iters, kappa=4.0)
-        tab[key] = dict(mu_hi=br["mu_hi"], mu_lo=br["mu_lo"], iters=br["iters"])
-        with open(_FILE, "w") as fh:
-            json.dump(tab, fh, indent=0, sort_keys=True)
-        print(f"{key} n {n[b]} K {K[b]} mu_hi {br['mu_hi']:.6g} mu_lo {br['mu_lo']:.6g} "
-              f"t {time.time() - t0:.0f}s", flush=True)
+    with Pool(workers) as pool:
+        for key, entry, nb, kb, sec in pool.imap_unordered(_bracket, todo):
+            tab[key] = entry
+            with open(_FILE + ".tmp", "w") as fh:
+                json.dump(tab, fh, indent=0, sort_keys=True)
+            os.replace(_FILE + ".tmp", _FILE)
+            print(f"{key} n {nb} K {kb} mu_hi {entry['mu_hi']:.9g} mu_lo {entry['mu_lo']:.9g} "
+                  f"({sec:.0f} s; {time.time() - t0:.0f} s in all)", flush=True)
 
 
 if __name__ == "__main__":

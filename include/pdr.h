@@ -106,6 +106,11 @@ typedef struct {
                               that neighbouring arcs re-read stay in L2);
                               1 = ordinary; 2 = non-temporal. Results are the
                               same bit for bit; batches always stream. */
+    int32_t height_layout; /* work layout of the excess -> height kernel: 0 =
+                              automatic, 1 = one thread per (vertex, 16-byte
+                              vector) item, 2 = one wave per (vertex, run of
+                              64-vector chunks). Heights are the same bit for
+                              bit (tuning). */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */
@@ -141,12 +146,12 @@ void pdr_default_options(pdr_options *opt);
  * Host arrays are deep-copied; opt may be NULL for the defaults.
  * Errors: PDR_ERR_INVALID for n < 1, m < 0, K < 1, a malformed CSR, a head
  * out of range, a self-loop, u or d negative or non-finite, s or t out of
- * range, s_k == t_k, a commodity endpoint of degree 0, or more commodities
- * than one arc kernel holds in the requested precision (a row of at most 8,192
- * vectors of 16 bytes: K <= 16,384 for PDR_FP64, K <= 32,768 for
- * PDR_FP32_BULK, whose FP64 polish then needs K <= 16,384); PDR_ERR_OOM if the
+ * range, s_k == t_k, a commodity endpoint of degree 0, or a requested tiling
+ * (lanes_per_arc, vec_per_lane) that does not cover the row; PDR_ERR_OOM if the
  * device buffers would not fit; PDR_ERR_DEVICE for a HIP failure. On failure
- * *out is set to NULL.
+ * *out is set to NULL. Rows of up to 8,192 vectors of 16 bytes (K <= 16,384 in
+ * PDR_FP64, K <= 32,768 in PDR_FP32_BULK) are held in registers by the arc
+ * kernels; longer rows are streamed (see pdr_tiling).
  */
 pdr_status pdr_init(pdr_ctx **out, int32_t n, int32_t m, const int64_t *row_ptr,
                     const int32_t *col, const double *u, int32_t K, const int32_t *s,
@@ -183,7 +188,9 @@ pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_
  * or when z stalls (four windows in a row whose smallest z is not below
  * (1 - 1e-3) times the smallest before), the flows are widened to FP64
  * exactly (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
- * The rate and stall tracking covers the windows of one call.
+ * The rate and stall tracking carries over from one call to the next, so a
+ * long run may be split into calls; pdr_set_state, pdr_set_state_noalloc and
+ * pdr_set_precision (and the hand-over itself) restart it.
  * sweeps_fp32 / sweeps_fp64 (may be NULL) receive the passes run in each
  * precision. Errors: PDR_ERR_INVALID for z_target <= 0, max_sweeps < 0 or
  * window < 1; PDR_ERR_NUMERIC for a non-finite objective; PDR_ERR_DEVICE.
@@ -286,8 +293,8 @@ pdr_status pdr_profile_sweeps(pdr_ctx *ctx, int64_t sweeps, double *kernel_ms);
  * the forward pass takes). Flows are kept every `checkpoint` passes
  * (0 = 16) and each segment is recomputed once during the reverse sweep;
  * working memory of about (T/checkpoint + checkpoint) m K + (checkpoint + 1)
- * n K doubles is allocated for the call. Needs method PDR_ESO and precision PDR_FP64
- * (PDR_ERR_STATE otherwise). If z(f^T) is not finite it returns
+ * n K doubles is allocated for the call. Needs method PDR_ESO, precision PDR_FP64
+ * and a register-resident row (K <= 16,384; PDR_ERR_STATE otherwise). If z(f^T) is not finite it returns
  * PDR_ERR_NUMERIC (the context is then at f^T, as after pdr_sweep) and writes
  * no gradient. Synchronizes. */
 pdr_status pdr_adjoint(pdr_ctx *ctx, int64_t T, int32_t checkpoint, double *z_out,
@@ -301,7 +308,12 @@ pdr_status pdr_adjoint(pdr_ctx *ctx, int64_t T, int32_t checkpoint, double *z_ou
 pdr_status pdr_measure_copy(int64_t bytes, int32_t iters, double *gbps);
 
 /* Query the automatic tiling: lanes per arc and vectors per lane of the arc
- * kernels, and the padded commodity stride Kp. */
+ * kernels, and the padded commodity stride Kp. A negative vec_per_lane means
+ * the row is longer than a register-resident tiling holds: one block of
+ * lanes_per_arc lanes per arc streams it in tiles of lanes_per_arc x
+ * (-vec_per_lane) vectors of 16 bytes, recomputing its values from f and h on
+ * each pass (ESO: one pass per step of the threshold iteration plus two;
+ * AGD/GDM: two). */
 pdr_status pdr_tiling(const pdr_ctx *ctx, int32_t *lanes_per_arc, int32_t *vec_per_lane,
                       int32_t *Kp);
 

@@ -105,6 +105,8 @@ int cover_nv(int64_t nvec, int L)
 Tiling auto_tiling(int32_t Kp, int32_t precision, int32_t method)
 {
     const int64_t nvec = Kp / vec_of(precision);
+    // rows longer than any register-resident tiling holds are streamed
+    if (nvec > pdr::max_tiling_vectors()) return pdr::streamed_tiling();
     // about five register vectors per lane: long rows get many lanes, and
     // the blocks stay small enough that several arcs share a CU
     int L = pow2ceil((nvec + 4) / 5);
@@ -120,6 +122,7 @@ Tiling auto_tiling(int32_t Kp, int32_t precision, int32_t method)
 bool tiling_covers(Tiling tl, int32_t Kp, int32_t precision)
 {
     const int64_t nvec = Kp / vec_of(precision);
+    if (tl.nv < 0) return pdr::tiling_supported(tl.lanes, tl.nv);  // streamed: any length
     return pdr::tiling_supported(tl.lanes, tl.nv) && (int64_t)tl.lanes * tl.nv >= nvec;
 }
 
@@ -132,13 +135,14 @@ pdr_status choose_tiling(pdr_ctx *c, int32_t precision, Tiling *out)
                                                     tl.lanes);
     }
     if (!tiling_covers(tl, c->Kp, precision)) {
-        char buf[240];
+        char buf[400];
         const int mv = pdr::max_tiling_vectors();
         snprintf(buf, sizeof buf,
-                 "no supported arc tiling covers K=%d (padded %d) in this precision "
-                 "(lanes %d x vectors %d; the longest row is %d vectors of 16 bytes: "
-                 "%d commodities in FP64, %d in FP32 bulk)",
-                 c->K, c->Kp, tl.lanes, tl.nv, mv, 2 * mv, 4 * mv);
+                 "the requested arc tiling (lanes %d x vectors %d) does not cover K=%d "
+                 "(padded %d) in this precision (a register-resident row holds at most %d "
+                 "vectors of 16 bytes: %d commodities in FP64, %d in FP32 bulk; longer rows "
+                 "take the automatic streamed tiling)",
+                 tl.lanes, tl.nv, c->K, c->Kp, mv, 2 * mv, 4 * mv);
         c->err = buf;
         return PDR_ERR_INVALID;
     }
@@ -182,6 +186,11 @@ void set_height_chunk(pdr_ctx *c)
         grid = 2 * kHeightGridAuto;
     c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : grid;
     c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : unroll;
+    // run-wise layout: about 8 wave items per resident wave of the 2,048-block grid
+    const int64_t nchunk = (nvec + 63) / 64;
+    const int64_t cps = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)c->n * nchunk /
+                                                                      (8 * 4 * (int64_t)kHeightGridAuto)));
+    c->g.height_run = c->req_height_layout == 2 ? (int32_t)cps : 0;
 }
 
 
@@ -406,6 +415,7 @@ void pdr_default_options(pdr_options *opt)
     opt->height_unroll = 0;
     opt->z_log_capacity = 0;
     opt->cache_policy = 0;
+    opt->height_layout = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -499,6 +509,8 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         return invalid("z_log_capacity must be 0 or a power of two up to 2^20");
     if (opt.cache_policy < 0 || opt.cache_policy > 2)
         return invalid("cache_policy must be 0, 1 or 2");
+    if (opt.height_layout < 0 || opt.height_layout > 2)
+        return invalid("height_layout must be 0, 1 or 2");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
@@ -525,6 +537,7 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
     c->req_height_grid = opt.height_blocks;
     c->req_height_unroll = opt.height_unroll;
     c->req_cache_policy = opt.cache_policy;
+    c->req_height_layout = opt.height_layout;
     if (opt.z_log_capacity > 0) c->zlog_cap = opt.z_log_capacity;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
@@ -673,7 +686,7 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         PDR_UP(c->d_vinc, vinc.data(), vinc.size());
     }
 #undef PDR_UP
-    c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,
+    c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,      0,
                     c->d_row_ptr, c->d_tails, c->d_heads, c->d_in_ptr, c->d_in_idx,
                     c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
                     c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder,
@@ -772,11 +785,12 @@ static pdr_status pdr_solve_body(pdr_ctx *c, double z_target, int64_t max_sweeps
     const double kappa = floor_factor > 0.0 ? floor_factor
                          : c->method == PDR_GDM ? kFloorFactorGdm : kFloorFactor;
     int64_t n32 = 0, n64 = 0, total = 0;
-    double best_before = std::numeric_limits<double>::infinity();
-    int stalled = 0;  // consecutive windows without a new lowest z
+    // the hand-over tracking continues where the previous call left it
+    double &best_before = c->solve_track.best_before;
+    int &stalled = c->solve_track.stalled;  // consecutive windows without a new lowest z
     // lowest z and passes of the recent FP32 windows (the descent rate is
     // measured over kRateWindows of them)
-    std::vector<std::pair<double, int64_t>> recent;
+    std::vector<std::pair<double, int64_t>> &recent = c->solve_track.recent;
     std::vector<double> zl;
     while (total < max_sweeps) {
         st = sync_ctrl(c);
@@ -816,11 +830,13 @@ static pdr_status pdr_solve_body(pdr_ctx *c, double z_target, int64_t max_sweeps
             // (GDM's objective is not monotone: one window can miss the last
             // trough and still be on the way down)
             stalled = cur < (1.0 - 1e-3) * best_before ? 0 : stalled + 1;
+            const double best_now = std::min(best_before, cur);
             if (near_floor || stalled >= kStallWindows) {
-                st = pdr_set_precision(c, PDR_FP64);
+                st = pdr_set_precision(c, PDR_FP64);  // also resets the tracking
                 if (st != PDR_OK) return st;
+            } else {
+                best_before = best_now;
             }
-            best_before = std::min(best_before, cur);
         }
     }
     if (sweeps_fp32) *sweeps_fp32 = n32;
@@ -1082,6 +1098,7 @@ static pdr_status stage_rows(pdr_ctx *c, const double *src, void *dst, double *s
 pdr_status set_state_impl(pdr_ctx *c, const double *f, const double *beta, const double *v,
                           int64_t t, double z_prev, double *staging, int64_t staging_doubles)
 {
+    c->solve_track = pdr_ctx::SolveTrack{};
     if (c->m > 0) {
         if (staging_doubles < c->K)
             return fail(c, PDR_ERR_INVALID, "one arc row does not fit the staging buffer");
@@ -1131,6 +1148,7 @@ pdr_status set_precision_impl(pdr_ctx *c, int32_t precision)
     }
     c->precision = precision;
     c->tiling = tl;
+    c->solve_track = pdr_ctx::SolveTrack{};
     set_height_chunk(c);
     set_cache_policy(c);
     PDR_CHECK(c, pdr::launch_rowsum(c->g, precision == PDR_FP64, c->tiling, cur_f(c), c->Fsum,
@@ -1186,6 +1204,9 @@ static pdr_status pdr_adjoint_body(pdr_ctx *c, int64_t T, int32_t checkpoint, do
         return fail(c, PDR_ERR_INVALID, "need T >= 0, checkpoint >= 0 and output arrays");
     if (c->method != PDR_ESO || c->precision != PDR_FP64)
         return fail(c, PDR_ERR_STATE, "the adjoint needs a PDR_ESO context in PDR_FP64");
+    if (c->tiling.nv < 0)
+        return fail(c, PDR_ERR_STATE,
+                    "the adjoint holds arc rows in registers: at most 16,384 commodities");
     const int64_t C = checkpoint > 0 ? checkpoint : 16;
     const int64_t nseg = (T + C - 1) / C;
     const size_t mK = (size_t)c->m * c->Kp, nK = (size_t)c->n * c->Kp;

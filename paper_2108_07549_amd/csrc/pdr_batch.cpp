@@ -451,6 +451,11 @@ static pdr_status pdr_batch_init_body(pdr_batch **out, int32_t B, const pdr_inst
             return init_fail_b(st, "instance " + std::to_string(i) + ": " + g_init_error);
         b->members[i]->batch_member = true;
         set_cache_policy(b->members[i]);  // the batch's kernels stream
+        if (b->members[i]->tiling.nv < 0)
+            return init_fail_b(PDR_ERR_INVALID,
+                               "instance " + std::to_string(i) +
+                                   ": batches hold arc rows in registers (at most 8,192 vectors "
+                                   "of 16 bytes: 16,384 commodities in FP64, 32,768 in FP32)");
     }
     e = hipMalloc((void **)&b->d_count, sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_count, sizeof(int32_t), hipHostMallocDefault);
@@ -738,6 +743,12 @@ static pdr_status pdr_batch_set_precision_body(pdr_batch *b, int32_t precision)
     if (!busable(b, &st)) return st;
     if (precision != PDR_FP64 && precision != PDR_FP32_BULK)
         return bfail(b, PDR_ERR_INVALID, "unknown precision");
+    const int64_t maxvec = pdr::max_tiling_vectors();
+    for (int32_t i = 0; i < b->B; ++i)  // batches hold rows in registers
+        if (b->members[i]->Kp / (precision == PDR_FP64 ? 2 : 4) > maxvec)
+            return bfail(b, PDR_ERR_INVALID,
+                         "instance " + std::to_string(i) +
+                             ": its row is longer than a batch holds in this precision");
     for (int32_t i = 0; i < b->B; ++i) {
         st = set_precision_impl(b->members[i], precision);
         if (st != PDR_OK) return member_fail(b, i, st);

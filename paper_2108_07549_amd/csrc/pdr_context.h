@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -61,6 +62,7 @@ struct pdr_ctx {
     int32_t req_height_grid = 0;           // 0 = automatic
     int32_t req_height_unroll = 0;         // 0 = automatic
     int32_t req_cache_policy = 0;          // 0 = automatic, 1 = ordinary, 2 = non-temporal
+    int32_t req_height_layout = 0;         // 0 = automatic, 1 = item-wise, 2 = run-wise
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
@@ -82,6 +84,15 @@ struct pdr_ctx {
     int64_t zlog_cap = pdr::kZLogCap;      // entries of the z log ring (power of two)
     bool batch_member = false;             // owned by a pdr_batch
     pdr::Ctrl *ctrl = nullptr;
+    // pdr_solve's hand-over tracking, carried from one call to the next:
+    // lowest z and passes of the recent FP32 windows, consecutive windows
+    // without a new lowest z, and the lowest z before the current window.
+    // Reset when the state or the precision is replaced.
+    struct SolveTrack {
+        std::vector<std::pair<double, int64_t>> recent;
+        int stalled = 0;
+        double best_before = HUGE_VAL;
+    } solve_track;
     // pinned host mirrors
     pdr::Ctrl *h_ctrl = nullptr;
     double *h_res = nullptr;

@@ -387,6 +387,173 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
     }
 }
 
+// Excess -> height with one wave per (vertex, run of commodity chunks): the
+// wave reads the vertex's record and its first kRunRows incidence entries
+// once, then walks its run of 64-vector chunks, each lane summing one 16-byte
+// vector of every incident row. The row loads of one chunk depend only on
+// those entries, so a wave keeps kRunRows loads in flight from chunk to chunk
+// instead of re-reading the record and the incidence list before every chunk.
+// Work items (run, vertex position) are run-major: the waves in flight cover
+// the same chunks of a window of consecutive vertices, so both reads of an
+// arc's chunk fall close together in time. Each element is summed in the same
+// order as height_core (in-arcs, then out-arcs, then injections), so the
+// heights are the same bit for bit.
+constexpr int kRunRows = 8;
+
+template <typename T, bool RESID, bool NT = true>
+__device__ __forceinline__ void height_core_run(const DevGraph &g, const T *__restrict__ f,
+                                                T *__restrict__ h, double *__restrict__ h64,
+                                                double *__restrict__ zpart,
+                                                double *__restrict__ maxpart,
+                                                const double *__restrict__ Fsum, int64_t blk,
+                                                int64_t nblk, int64_t part)
+{
+    constexpr int V = VecT<T>::N;
+    constexpr int U = kRunRows;
+    constexpr bool kNoise = !RESID && sizeof(T) == 4;
+    __shared__ double sh[12];
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = (int)threadIdx.x >> 6;
+    const int nvec = g.Kp / V;
+    const int64_t Kp = g.Kp;
+    const int nchunk = (nvec + 63) / 64;
+    const int cps = g.height_run;
+    const int nrun = (nchunk + cps - 1) / cps;
+    const int64_t witems = (int64_t)nrun * g.n;
+    double zs = 0.0, mx = 0.0, ns = 0.0;
+    for (int64_t wi = blk * 4 + wv; wi < witems; wi += nblk * 4) {
+        const int s = (int)(wi / g.n);
+        const int pos = (int)(wi - (int64_t)s * g.n);
+        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
+        const int4 vj = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
+        const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
+        const int dg = p1 - p0;
+        int e[U];
+#pragma unroll
+        for (int b = 0; b < U; ++b) e[b] = p0 + b < p1 ? g.vinc[p0 + b] : -1;
+        const int c0 = s * cps;
+        const int c1 = c0 + cps < nchunk ? c0 + cps : nchunk;
+        for (int c = c0; c < c1; ++c) {
+            const int q = c * 64 + lane;
+            if (q >= nvec) break;
+            const int k0 = q * V;
+            double acc[V];
+            float mag[V];
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                acc[w] = 0.0;
+                mag[w] = 0.0f;
+            }
+            T x[U][V];
+#pragma unroll
+            for (int b = 0; b < U; ++b)
+                if (e[b] >= 0) load_vec(f + (int64_t)e[b] * Kp + k0, x[b]);
+#pragma unroll
+            for (int b = 0; b < U; ++b)
+                if (e[b] >= 0) {
+                    const double sg = p0 + b < pin ? 1.0 : -1.0;
+#pragma unroll
+                    for (int w = 0; w < V; ++w) {
+                        acc[w] += sg * (double)x[b][w];
+                        if constexpr (kNoise) mag[w] += fabsf((float)x[b][w]);
+                    }
+                }
+            // incident rows beyond the first U, in batches of U
+            for (int p = p0 + U; p < p1; p += U) {
+                int e2[U];
+#pragma unroll
+                for (int b = 0; b < U; ++b) e2[b] = g.vinc[p + b < p1 ? p + b : p];
+                T y[U][V];
+#pragma unroll
+                for (int b = 0; b < U; ++b) load_vec(f + (int64_t)e2[b] * Kp + k0, y[b]);
+#pragma unroll
+                for (int b = 0; b < U; ++b)
+                    if (p + b < p1) {
+                        const double sg = p + b < pin ? 1.0 : -1.0;
+#pragma unroll
+                        for (int w = 0; w < V; ++w) {
+                            acc[w] += sg * (double)y[b][w];
+                            if constexpr (kNoise) mag[w] += fabsf((float)y[b][w]);
+                        }
+                    }
+            }
+            if (k0 <= vj.w && k0 + V > vj.z) {
+                for (int p = vj.x; p < vj.y; ++p) {
+                    const int k = g.inj_k[p] - k0;
+                    const double val = g.inj_val[p];
+#pragma unroll
+                    for (int w = 0; w < V; ++w)
+                        if (w == k) {
+                            acc[w] += val;
+                            if constexpr (kNoise) mag[w] += (float)fabs(val);
+                        }
+                }
+            }
+            T hv[V];
+            double hd[V];
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const double hh = dg > 0 ? acc[w] / (double)dg : 0.0;
+                hd[w] = hh;
+                hv[w] = (T)hh;
+                zs += acc[w] * hh;
+                if (RESID) mx = fmax(mx, fabs(acc[w]));
+                if constexpr (kNoise) {
+                    const double r = kFp32Unit * (double)mag[w];
+                    if (dg > 0) ns += r * r / (double)dg;
+                }
+            }
+            if constexpr (RESID) {
+                double *dst = h64 + (int64_t)i * Kp + k0;
+#pragma unroll
+                for (int w = 0; w < V; w += 2)
+                    *reinterpret_cast<double2 *>(dst + w) = make_double2(hd[w], hd[w + 1]);
+            } else {
+                store_vec_s<NT>(h + (int64_t)i * Kp + k0, hv);
+            }
+        }
+    }
+    double ps = 0.0;
+    if constexpr (!RESID) {
+        for (int64_t e = part * 256 + threadIdx.x; e < g.m; e += nblk * 256) {
+            const double over = Fsum[e] - g.u[e];
+            if (over > 0.0) ps += over * over;
+        }
+    }
+    zs = wave_sum(zs);
+    if (RESID) mx = wave_max(mx);
+    else ps = wave_sum(ps);
+    if constexpr (kNoise) ns = wave_sum(ns);
+    if (lane == 0) {
+        sh[wv] = zs;
+        sh[4 + wv] = RESID ? mx : ps;
+        sh[8 + wv] = ns;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        zpart[part] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        if (RESID) {
+            maxpart[part] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+        } else {
+            zpart[nblk + part] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+            zpart[2 * nblk + part] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
+        }
+    }
+}
+
+template <typename T, bool RESID, bool NT>
+__global__ __launch_bounds__(256) void k_height_run(DevGraph g, const T *__restrict__ f,
+                                                    T *__restrict__ h, double *__restrict__ h64,
+                                                    double *__restrict__ zpart,
+                                                    double *__restrict__ maxpart,
+                                                    const double *__restrict__ Fsum,
+                                                    const Ctrl *__restrict__ ctrl)
+{
+    if (!RESID && ctrl->stopped) return;
+    height_core_run<T, RESID, NT>(g, f, h, h64, zpart, maxpart, Fsum,
+                                  xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
+}
+
 // Eight waves per SIMD (at most 64 VGPRs) for the unrolls up to 4, so that the
 // default grid (8 blocks of 4 waves on each of the 256 CUs) is resident at
 // once and no block starts late.
@@ -837,6 +1004,265 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
             for (int w = 0; w < V; ++w) fs[0] += (double)x[w];
         }
     }
+    group_sum<L, 1>(fs, lds, phase);
+    if (lane == 0) Fsum[e] = fs[0];
+}
+
+// ----------------------------------------------------------------- long rows
+// Rows longer than the register-resident arc kernels hold (more than
+// kStreamMinVectors 16-byte vectors): one block of kStreamLanes lanes per
+// arc streams the row in tiles of kStreamLanes x TV vectors and recomputes
+// the row's values from f, h_i and h_j on every pass over it, with the same
+// per-element arithmetic as the resident kernels. PDR-ESO needs one pass for
+// the first sums, one per step of the threshold iteration and one for the
+// update; PDR-AGD and PDR-GDM one for their sums and one for the update (if
+// accepted). Loads are ordinary (the passes re-read the row); the final
+// stores are streaming.
+constexpr int kStreamLanes = 1024;
+// vectors per lane of one tile; Tiling{kStreamLanes, -kStreamTile} names the
+// streamed arc kernels
+constexpr int kStreamTile = 4;
+
+template <typename T>
+__device__ __forceinline__ void stream_c(const T *__restrict__ fe, const T *__restrict__ hi,
+                                         const T *__restrict__ hj, int q, T (&c)[VecT<T>::N])
+{
+    constexpr int V = VecT<T>::N;
+    T a[V], b[V], x[V];
+    load_vec(fe + q * V, x);
+    load_vec(hi + q * V, a);
+    load_vec(hj + q * V, b);
+#pragma unroll
+    for (int w = 0; w < V; ++w) c[w] = (T)0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
+}
+
+template <typename T, int TV, bool CAP>
+__device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict__ f,
+                                               const T *__restrict__ h, double *__restrict__ Fsum,
+                                               int64_t slot, int lane, double *lds)
+{
+    constexpr int L = kStreamLanes, V = VecT<T>::N;
+    int phase = 0;
+    const int64_t e = g.aorder[slot];
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    T *fe = f + e * Kp;
+    const T *hi = h + (int64_t)g.tails[e] * Kp;
+    const T *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+    double red[2] = {0.0, 0.0};
+    for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+        for (int v = 0; v < TV; ++v) {
+            const int q = base + v * L + lane;
+            if (q < nvec) {
+                T c[V];
+                stream_c(fe, hi, hj, q, c);
+#pragma unroll
+                for (int w = 0; w < V; ++w)
+                    if (c[w] > (T)0) {
+                        red[0] += (double)c[w];
+                        red[1] += 1.0;
+                    }
+            }
+        }
+    group_sum<L, 2>(red, lds, phase);
+    double Ssum = red[0], P = red[1];
+    double half = 0.0;
+    if (Ssum > u) {
+        double theta = 0.0;
+        for (;;) {
+            half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
+            const double th = fmax(theta, half);
+            double r2[2] = {0.0, 0.0};
+            for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+                for (int v = 0; v < TV; ++v) {
+                    const int q = base + v * L + lane;
+                    if (q < nvec) {
+                        T c[V];
+                        stream_c(fe, hi, hj, q, c);
+#pragma unroll
+                        for (int w = 0; w < V; ++w) {
+                            const double cc = (double)c[w];
+                            if (cc > th) {
+                                r2[0] += cc;
+                                r2[1] += 1.0;
+                            }
+                        }
+                    }
+                }
+            group_sum<L, 2>(r2, lds, phase);
+            if (r2[1] == P || (CAP && r2[1] == 0.0)) break;
+            Ssum = r2[0];
+            P = r2[1];
+            theta = th;
+        }
+    }
+    double fs[1] = {0.0};
+    for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+        for (int v = 0; v < TV; ++v) {
+            const int q = base + v * L + lane;
+            if (q < nvec) {
+                T c[V], o[V];
+                stream_c(fe, hi, hj, q, c);
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double val = (double)c[w] - half;
+                    o[w] = (T)(val > 0.0 ? val : 0.0);
+                    fs[0] += (double)o[w];
+                }
+                store_vec_s<true>(fe + q * V, o);
+            }
+        }
+    group_sum<L, 1>(fs, lds, phase);
+    if (lane == 0) Fsum[e] = fs[0];
+}
+
+template <typename T, int TV, bool CAP>
+__global__ __launch_bounds__(kStreamLanes) void k_eso_stream(DevGraph g, T *__restrict__ f,
+                                                             const T *__restrict__ h,
+                                                             double *__restrict__ Fsum,
+                                                             const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    __shared__ double lds[2 * kRedMax * (kStreamLanes / 64)];
+    eso_arc_stream<T, TV, CAP>(g, f, h, Fsum, xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x,
+                               lds);
+}
+
+// AGD (vel == nullptr) or GDM arc step on a streamed row: the first pass sums
+// df, df (df - g) and the new row's values; an accepted step recomputes and
+// stores the row in a second pass.
+template <typename T, int TV, bool GDM>
+__device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict__ f,
+                                               T *__restrict__ vel, const T *__restrict__ h,
+                                               double *__restrict__ Fsum, double *__restrict__ beta,
+                                               const AgdParams &prm, const Ctrl *__restrict__ ctrl,
+                                               int64_t slot, int lane, double *lds)
+{
+    constexpr int L = kStreamLanes, V = VecT<T>::N;
+    int phase = 0;
+    const int64_t e = g.aorder[slot];
+    const int64_t Kp = g.Kp;
+    const int nvec = g.Kp / V;
+    T *fe = f + e * Kp;
+    T *ve = GDM ? vel + e * Kp : nullptr;
+    const T *hi = h + (int64_t)g.tails[e] * Kp;
+    const T *hj = h + (int64_t)g.heads[e] * Kp;
+    const double u = g.u[e];
+    const double F = Fsum[e];
+    const double psi = F > u ? F - u : 0.0;
+    const double b = beta[e];
+    const double gam = prm.gamma;
+    // the stepped values of vector q: new flows (and velocities)
+    auto step = [&](int q, T (&nf)[V], T (&nv)[V], double (&r)[3]) {
+        T a[V], bb[V], x[V], w0[V];
+        load_vec(fe + q * V, x);
+        if constexpr (GDM) load_vec(ve + q * V, w0);
+        load_vec(hi + q * V, a);
+        load_vec(hj + q * V, bb);
+#pragma unroll
+        for (int w = 0; w < V; ++w) {
+            const double gg = (double)(a[w] - bb[w]);
+            const double fx = (double)x[w];
+            const double st = b * (gg - psi);
+            const double df = st > -fx ? st : -fx;
+            if constexpr (GDM) {
+                const double vn = gam * (double)w0[w] + df;
+                const double fn = fx + vn;
+                nv[w] = (T)vn;
+                nf[w] = (T)(fn > 0.0 ? fn : 0.0);
+            } else {
+                nf[w] = (T)(fx + df);
+            }
+            r[0] += df;
+            r[1] += df * (df - gg);
+            r[2] += (double)nf[w];
+        }
+    };
+    double red[3] = {0.0, 0.0, 0.0};
+    for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+        for (int v = 0; v < TV; ++v) {
+            const int q = base + v * L + lane;
+            if (q < nvec) {
+                T nf[V], nv[V];
+                step(q, nf, nv, red);
+            }
+        }
+    group_sum<L, 3>(red, lds, phase);
+    const double before = F - u, after = F + red[0] - u;
+    const double dcong = (before > 0.0 && after > 0.0)
+                             ? red[0] * (before + 0.5 * red[0])
+                             : 0.5 * ((after > 0.0 ? after * after : 0.0) -
+                                      (before > 0.0 ? before * before : 0.0));
+    const bool accept = dcong + red[1] <= 0.0;
+    if (accept) {
+        for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+            for (int v = 0; v < TV; ++v) {
+                const int q = base + v * L + lane;
+                if (q < nvec) {
+                    T nf[V], nv[V];
+                    double dummy[3] = {0.0, 0.0, 0.0};
+                    step(q, nf, nv, dummy);
+                    store_vec_s<true>(fe + q * V, nf);
+                    if constexpr (GDM) store_vec_s<true>(ve + q * V, nv);
+                }
+            }
+    }
+    if (lane == 0) {
+        double nb = b;
+        if (!accept) nb = fmax(prm.beta_min, nb * prm.alpha_dec);
+        if (prm.inc_period > 0 && (ctrl->t_pass % prm.inc_period) == 0)
+            nb = fmin(prm.beta_max, nb * prm.alpha_inc);
+        beta[e] = nb;
+        if (accept) Fsum[e] = red[2];
+    }
+}
+
+template <typename T, int TV, bool GDM>
+__global__ __launch_bounds__(kStreamLanes) void k_agd_stream(DevGraph g, T *__restrict__ f,
+                                                             T *__restrict__ vel,
+                                                             const T *__restrict__ h,
+                                                             double *__restrict__ Fsum,
+                                                             double *__restrict__ beta,
+                                                             AgdParams prm,
+                                                             const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    __shared__ double lds[2 * kRedMax * (kStreamLanes / 64)];
+    agd_arc_stream<T, TV, GDM>(g, f, vel, h, Fsum, beta, prm, ctrl,
+                               xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x, lds);
+}
+
+// Fsum of a streamed row.
+template <typename T, int TV>
+__global__ __launch_bounds__(kStreamLanes) void k_rowsum_stream(DevGraph g,
+                                                                const T *__restrict__ f,
+                                                                double *__restrict__ Fsum)
+{
+    constexpr int V = VecT<T>::N, L = kStreamLanes;
+    __shared__ double lds[2 * kRedMax * (L / 64)];
+    int phase = 0;
+    const int64_t e = g.aorder[xcd_remap(blockIdx.x, gridDim.x)];
+    const int nvec = g.Kp / V;
+    const T *fe = f + e * (int64_t)g.Kp;
+    double fs[1] = {0.0};
+    const int lane = (int)threadIdx.x;
+    for (int base = 0; base < nvec; base += L * TV)
+#pragma unroll
+        for (int v = 0; v < TV; ++v) {
+            const int q = base + v * L + lane;
+            if (q < nvec) {
+                T x[V];
+                load_vec(fe + q * V, x);
+#pragma unroll
+                for (int w = 0; w < V; ++w) fs[0] += (double)x[w];
+            }
+        }
     group_sum<L, 1>(fs, lds, phase);
     if (lane == 0) Fsum[e] = fs[0];
 }

@@ -34,6 +34,8 @@ struct DevGraph {
     int32_t height_cv;       // vectors per commodity chunk in the height kernel
     int32_t height_grid;     // blocks of the height kernel (<= kHeightBlocksMax)
     int32_t height_unroll;   // incident rows loaded together per thread (1, 2 or 4)
+    int32_t height_run;      // > 0: the run-wise height kernel (k_height_run) with
+                             // this many 64-vector chunks per wave item; 0: k_height
     const int32_t *row_ptr;  // n+1: out-arcs of i are [row_ptr[i], row_ptr[i+1])
     const int32_t *tails;    // m
     const int32_t *heads;    // m
@@ -69,11 +71,16 @@ struct AgdParams {
 };
 
 // Arc-kernel tiling: `lanes` lanes cooperate on one arc, each holding up to
-// `nv` 16-byte vectors of the arc's commodity row in registers.
+// `nv` 16-byte vectors of the arc's commodity row in registers. A negative nv
+// names the streamed kernels for rows longer than any resident tiling: the
+// lanes pass over the row in tiles of lanes x (-nv) vectors (Tiling{1024, -4},
+// streamed_tiling()).
 struct Tiling {
     int lanes;
     int nv;
 };
+// The one streamed tiling.
+Tiling streamed_tiling();
 
 // One instance of a batch as the batched kernels see it (device-resident
 // array, one entry per instance). All instances of a batch share one storage

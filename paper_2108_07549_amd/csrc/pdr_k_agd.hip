@@ -26,6 +26,19 @@ hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
                       hipStream_t st)
 {
     if (g.m == 0) return hipSuccess;
+    if (tl.lanes == kStreamLanes && tl.nv == -kStreamTile) {  // streamed long rows
+        const unsigned nb = (unsigned)g.m;
+        constexpr int TV = kStreamTile;
+        if (fp64 && vel)
+            k_agd_stream<double, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, (double *)vel, (const double *)h, Fsum, beta, prm, ctrl);
+        else if (fp64)
+            k_agd_stream<double, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, nullptr, (const double *)h, Fsum, beta, prm, ctrl);
+        else if (vel)
+            k_agd_stream<float, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, (float *)vel, (const float *)h, Fsum, beta, prm, ctrl);
+        else
+            k_agd_stream<float, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, nullptr, (const float *)h, Fsum, beta, prm, ctrl);
+        return hipGetLastError();
+    }
 #define PDR_AGD_CASE(L_, NV_)                                                                  \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                      \
         const unsigned nb = arc_blocks(g.m, L_);                                               \

@@ -23,6 +23,19 @@ hipError_t launch_eso(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
                       double *Fsum, const Ctrl *ctrl, bool cap, hipStream_t st)
 {
     if (g.m == 0) return hipSuccess;
+    if (tl.lanes == kStreamLanes && tl.nv == -kStreamTile) {  // streamed long rows
+        const unsigned nb = (unsigned)g.m;
+        constexpr int TV = kStreamTile;
+        if (fp64 && cap)
+            k_eso_stream<double, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, (const double *)h, Fsum, ctrl);
+        else if (fp64)
+            k_eso_stream<double, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, (const double *)h, Fsum, ctrl);
+        else if (cap)
+            k_eso_stream<float, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, (const float *)h, Fsum, ctrl);
+        else
+            k_eso_stream<float, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, (const float *)h, Fsum, ctrl);
+        return hipGetLastError();
+    }
 #define PDR_ESO_CASE(L_, NV_)                                                                    \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
         const unsigned nb = arc_blocks(g.m, L_);                                                 \

@@ -23,6 +23,13 @@ hipError_t launch_rowsum(const DevGraph &g, bool fp64, Tiling tl, const void *f,
                          hipStream_t st)
 {
     if (g.m == 0) return hipSuccess;
+    if (tl.lanes == kStreamLanes && tl.nv == -kStreamTile) {  // streamed long rows
+        if (fp64)
+            k_rowsum_stream<double, kStreamTile><<<(unsigned)g.m, kStreamLanes, 0, st>>>(g, (const double *)f, Fsum);
+        else
+            k_rowsum_stream<float, kStreamTile><<<(unsigned)g.m, kStreamLanes, 0, st>>>(g, (const float *)f, Fsum);
+        return hipGetLastError();
+    }
 #define PDR_ROW_CASE(L_, NV_)                                                                    \
     if (tl.lanes == L_ && tl.nv == NV_) {                                                        \
         const unsigned nb = arc_blocks(g.m, L_);                                                 \

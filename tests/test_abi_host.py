@@ -135,12 +135,14 @@ def test_init_rejects_invalid_options(opts, fragment):
     assert ei.value.status == 1 and fragment in ei.value.message
 
 
-def test_oversize_commodity_row_is_rejected():
+def test_requested_tiling_that_misses_the_row_is_rejected():
+    """A requested register-resident tiling shorter than the row is refused
+    before any device call (rows that long take the automatic streamed tiling)."""
     a = _good()
-    K = 40000  # FP64 rows above 1024 lanes x 8 vectors x 2 values are not supported
+    K = 40000  # FP64 rows above 1024 lanes x 8 vectors x 2 values
     with pytest.raises(pdr.PdrError) as ei:
         pdr.Context(a["n"], a["row_ptr"], a["col"], a["u"], np.zeros(K, np.int32),
-                    np.full(K, 2, np.int32), np.ones(K))
+                    np.full(K, 2, np.int32), np.ones(K), lanes_per_arc=1024, vec_per_lane=8)
     assert ei.value.status == 1 and "tiling" in ei.value.message
 
 

@@ -193,9 +193,10 @@ def test_ragged_commodity_counts(method, K):
 
 
 @pytest.mark.parametrize("method", ALL)
-def test_longest_supported_commodity_row_fp64(method):
-    """K = 16,384, the longest FP64 row an arc kernel holds (1024 lanes x 8
-    vectors of two commodities), on a congested 210-point k-NN graph."""
+def test_longest_register_resident_row_fp64(method):
+    """K = 16,384, the longest FP64 row an arc kernel holds in registers (1024
+    lanes x 8 vectors of two commodities), on a congested 210-point k-NN graph;
+    one more commodity takes the streamed kernels."""
     gm, om = METHODS[method]
     inst = recipe_small("knn", 210, 16384, seed=77, u_range=(20, 1600), d_range=(1, 5))
     T = 8
@@ -207,28 +208,66 @@ def test_longest_supported_commodity_row_fp64(method):
     st, zo = oracle.run(inst, om, T)
     assert np.max(np.abs(f - st.f)) <= flow_tol(inst)
     assert np.allclose(zg, zo, rtol=1e-9, atol=0)
-    with pytest.raises(pdr.PdrError) as ei:
-        ctx_for(recipe_small("knn", 210, 16385, seed=77), gm)
-    assert ei.value.status == 1 and "16384 commodities in FP64" in ei.value.message
+    with ctx_for(recipe_small("knn", 210, 16385, seed=77), gm) as c:
+        assert c.tiling() == (1024, -4, 16416)
 
 
-def test_longest_supported_commodity_row_fp32():
-    """K = 32,768, the longest FP32-bulk row (1024 lanes x 8 vectors of four);
-    its FP64 polish does not fit one arc kernel and is refused."""
-    inst = recipe_small("knn", 210, 32768, seed=78, u_range=(40, 3200), d_range=(1, 5))
-    T = 8
-    with ctx_for(inst, pdr.ESO, pdr.FP32_BULK) as c:
-        assert c.tiling() == (1024, 8, 32768)
+# Long rows (streamed kernels): Table 1's largest commodity counts (K = 32,000
+# for Cgd15, 81,430 for Cpl2500) on k-NN graphs with enough points for K
+# distinct OD pairs, capacities low enough that arcs congest within the run.
+LONG_ROWS = [(16385, 210, (20, 1600)), (32000, 300, (40, 3000)), (81430, 300, (100, 8000))]
+
+
+@pytest.mark.parametrize("K,npts,urange", LONG_ROWS)
+@pytest.mark.parametrize("method", ALL)
+def test_streamed_long_rows_fp64(method, K, npts, urange):
+    gm, om = METHODS[method]
+    inst = recipe_small("knn", npts, K, seed=K % 97, u_range=urange, d_range=(1, 5))
+    T = 5
+    with ctx_for(inst, gm) as c:
+        assert c.tiling()[:2] == (1024, -4)
         c.sweep(T)
         f = c.flows()
         zg = c.z_log(0, T)
-        with pytest.raises(pdr.PdrError) as ei:
-            c.set_precision(pdr.FP64)
-        assert ei.value.status == 1
-        assert np.array_equal(c.flows(), f)  # a refused widening leaves the state alone
+        bg = c.learning_rates()
+        res = c.residual()
+    st, zo = oracle.run(inst, om, T)
+    err = float(np.max(np.abs(f - st.f)))
+    say("streamed", method, "K", K, "m", inst.m, "max|df|", err, "max psi", res["max_congestion"])
+    assert err <= flow_tol(inst)
+    assert np.allclose(zg, zo, rtol=1e-9, atol=0)
+    if gm in (pdr.AGD, pdr.GDM):
+        assert np.array_equal(bg, st.beta)
+    assert oracle.report(inst, st.f)["max_congestion"] > 0  # the congested branches ran
+
+
+def test_long_row_fp32_bulk_and_fp64_polish():
+    """K = 32,768 in FP32 bulk (the longest register-resident FP32 row) widens
+    exactly to FP64, where the row is streamed, and the run continues in
+    parity with the oracle resumed from the widened flows."""
+    inst = recipe_small("knn", 300, 32768, seed=78, u_range=(40, 3000), d_range=(1, 5))
+    T = 6
+    with ctx_for(inst, pdr.ESO, pdr.FP32_BULK) as c:
+        assert c.tiling() == (1024, 8, 32768)
+        c.sweep(T)
+        f32 = c.flows()
+        zg = c.z_log(0, T)
+        c.set_precision(pdr.FP64)
+        assert c.tiling()[:2] == (1024, -4)
+        assert np.array_equal(c.flows(), f32)  # exact widening
+        c.sweep(4)
+        f64 = c.flows()
+        zlast = c.z_log(T + 3, 1)[0]
     st, zo = oracle.run(inst, oracle.ESO, T)
-    assert np.max(np.abs(f - st.f)) <= 1e-3 * float(np.max(inst.u))
-    assert np.allclose(zg, zo, rtol=1e-4, atol=0)
+    assert np.max(np.abs(f32 - st.f)) <= T * 2.0 ** -24 * float(np.max(inst.u))
+    assert np.allclose(zg, zo, rtol=T * 2.0 ** -24, atol=0)
+    st2 = oracle.State(inst, oracle.ESO)
+    st2.f = f32.copy()
+    st2.t = T
+    st2.z_prev = zg[-1]
+    zo2 = st2.run(4)
+    assert np.max(np.abs(f64 - st2.f)) <= flow_tol(inst)
+    assert zlast == pytest.approx(zo2[-1], rel=1e-9)
 
 
 # ------------------------------------------------------------------ edge cases
@@ -678,3 +717,49 @@ def test_solve_fp64_and_fp32_polish_reach_target(method):
         res = c.residual()
         say("solve fp32+polish", method, n32, n64)
     assert res["z"] <= 1e-20 and n32 > 0 and n64 > 0
+
+
+@pytest.mark.parametrize("method", ["eso", "gdm"])
+def test_solve_split_into_calls_equals_one_call(method):
+    """pdr_solve's hand-over tracking carries over between calls: a run split
+    into calls of ten windows hands over at the same pass and ends in the same
+    state as one call."""
+    gm, _ = METHODS[method]
+    inst = recipe_small("grid", 5, 20, seed=3, u_range=(5, 20), d_range=(1, 5))
+    with ctx_for(inst, gm, pdr.FP32_BULK) as c:
+        one = c.solve(1e-20, 200_000, 128)
+        f_one, r_one = c.flows(), c.residual()
+    with ctx_for(inst, gm, pdr.FP32_BULK) as c:
+        n32 = n64 = 0
+        while True:
+            a, b = c.solve(1e-20, 1280, 128)
+            n32, n64 = n32 + a, n64 + b
+            if a + b == 0 or c.residual()["stopped"] or n32 + n64 >= 200_000:
+                break
+        f_many, r_many = c.flows(), c.residual()
+    say("solve split", method, one, (n32, n64))
+    assert one[1] > 0 and (n32, n64) == one
+    assert np.array_equal(f_one, f_many) and r_one["z"] == r_many["z"]
+
+
+@pytest.mark.parametrize("precision", [pdr.FP64, pdr.FP32_BULK])
+@pytest.mark.parametrize("method", ["eso", "gdm"])
+def test_height_layouts_give_the_same_iterates(method, precision):
+    """The item-wise and the run-wise excess -> height kernels sum every
+    element in the same order: flows and heights are equal bit for bit (the
+    objective's partial sums are grouped differently, so z agrees to rounding),
+    for rows shorter than one chunk, ragged rows and rows of many chunks."""
+    gm, _ = METHODS[method]
+    cases = [recipe_small("knn", 200, 37, seed=9, u_range=(5, 40), d_range=(1, 6)),
+             recipe_small("grid", 9, 1000, seed=10, u_range=(20, 200), d_range=(1, 5)),
+             recipe_small("knn", 60, 3001, seed=11, u_range=(50, 900), d_range=(1, 5))]
+    for inst in cases:
+        out = []
+        for layout in (1, 2):
+            with ctx_for(inst, gm, precision, height_layout=layout) as c:
+                c.sweep(30)
+                out.append((c.flows(), c.heights(), c.z_log(0, 30)))
+        say("height layouts", method, precision, inst.meta.get("recipe"))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1])
+        assert np.allclose(out[0][2], out[1][2], rtol=1e-12, atol=0)
