@@ -233,6 +233,61 @@ def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
                 certified=cert, generate_s=gen_s, init_s=init_s, auto=auto, tuned=after)
 
 
+def batch_verdicts(pdr, insts, method, seconds, chunk=2000):
+    """The batch swept in FP64 for about `seconds` of wall time; every member's
+    verdict (Farkas gap > tau: infeasible; z <= 1e-8: feasible) against its
+    certified label (gen.batch: column-generation brackets)."""
+    with pdr.Batch(insts, method=method, precision=pdr.FP64) as b:
+        t0 = time.perf_counter()
+        passes = 0
+        while True:
+            b.sweep(chunk)
+            pdr.device_synchronize()
+            passes += chunk
+            if time.perf_counter() - t0 >= seconds:
+                break
+        sec = time.perf_counter() - t0
+        out = dict(passes=passes, seconds=sec, decided=0, agree=0, disagree=0, undecided=0,
+                   by_label={})
+        for q, inst in enumerate(insts):
+            v = b.member(q).residual()["verdict"]
+            lab = inst.meta.get("certified", "uncertified")
+            row = out["by_label"].setdefault(lab, dict(members=0, feasible=0, infeasible=0,
+                                                       undecided=0))
+            row["members"] += 1
+            row[v] += 1
+            if v == "undecided":
+                out["undecided"] += 1
+            else:
+                out["decided"] += 1
+                out["agree" if v == lab else "disagree"] += 1
+    return out
+
+
+def time_long_rows(pdr, steps, warmup):
+    """Sweeps of the 2,500-vertex k-NN instance with K = 81,430 (rows streamed
+    by the arc kernels), per method and precision, against the HBM roofline of
+    the two-phase sweep's algorithmic bytes."""
+    from gen.instance import load_instance
+    inst = load_instance("knn2500_k81430")
+    n, m, K = inst.n, inst.m, inst.K
+    out = dict(workload="knn2500_k81430", n=n, m=m, K=K, lf_bracket=inst.meta.get("lf_bracket"))
+    for name, meth, prec in (("eso_fp64", pdr.ESO, pdr.FP64), ("eso_fp32", pdr.ESO, pdr.FP32_BULK),
+                             ("agd_fp64", pdr.AGD, pdr.FP64), ("gdm_fp64", pdr.GDM, pdr.FP64)):
+        r = time_variant(pdr, inst, meth, prec, steps, warmup)
+        w = 8 if prec == pdr.FP64 else 4
+        sweep_bytes = w * (3 * m * K + 2 * n * K) + (2 * w * m * K if meth == pdr.GDM else 0)
+        arc_bytes = w * (2 * m * K + n * K) + (2 * w * m * K if meth == pdr.GDM else 0)
+        arc_ms = r["kernel_ms_avg"]["arc"]
+        out[name] = dict(ms_per_step=r["ms_per_step"], updates_per_s=r["updates_per_s"],
+                         kernel_ms_avg=r["kernel_ms_avg"], tiling=r["tiling"],
+                         sweep_frac=sweep_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         arc_frac=arc_bytes / (arc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        print(f"[bench] long rows {name}: {r['ms_per_step']:.3f} ms/sweep", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def time_adjoint(pdr, inst, T, checkpoint, forward_ms):
     """Wall time of pdr_adjoint (T forward passes, the recomputation and the
     reverse sweep) from f = 0, and its cost in forward-sweep equivalents."""
@@ -321,6 +376,10 @@ def main():
                     help="skip the batched 256-instance workload")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint (reverse-mode gradient) timing")
+    ap.add_argument("--no-long-rows", action="store_true",
+                    help="skip the K = 81,430 (streamed rows) workload")
+    ap.add_argument("--verdict-seconds", type=float, default=30.0,
+                    help="wall time of the batch verdict run (0: skip)")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
     ap.add_argument("--ttr-workload", default="knn2500_k1000",
@@ -444,7 +503,14 @@ def main():
             print(f"[bench] batch {name}: auto {r['auto']['ms_per_step']:.3f} ms/sweep, tuned "
                   f"{r['tuned']['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
             bat[name] = r
+        if args.verdict_seconds > 0:
+            from gen.batch import recipe_batch
+            v = batch_verdicts(pdr, recipe_batch(256, 4), pdr.GDM, args.verdict_seconds)
+            print(f"[bench] batch verdicts: {v}", file=sys.stderr, flush=True)
+            bat["verdicts_gdm_fp64"] = v
         out["batch"] = bat
+    if not args.no_long_rows:
+        out["long_rows"] = time_long_rows(pdr, min(args.steps, 20), min(args.warmup, 3))
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_sweeps} oracle sweeps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sweeps, args.cpu_single_sweeps)

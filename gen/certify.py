@@ -35,8 +35,9 @@ def main(argv):
                 return
             table[key] = dict(mu_hi=br["mu_hi"], mu_lo=br["mu_lo"], iters=br["iters"],
                               columns=br["columns"], gap=br["mu_hi"] / br["mu_lo"] - 1.0)
-            with open(_LF_FILE, "w") as fh:
+            with open(_LF_FILE + ".tmp", "w") as fh:
                 json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(_LF_FILE + ".tmp", _LF_FILE)
             print(key, table[key], flush=True)
 
         br = congestion_bracket(inst, verbose=True, mu_lo0=lo0, on_iter=save,

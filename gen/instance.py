@@ -142,10 +142,21 @@ def recipe_small(kind: str, size: int, K: int, seed: int, u_range=(5, 20), d_ran
     return random_instance(rp, col, K, seed, u_range, d_range, dict(recipe=f"{kind}{size}_k{K}"))
 
 
+def recipe_knn2500_k81430(seed: int = 6) -> Instance:
+    """Random geometric 4-NN graph, n 2500; K 81,430 (the commodity count of the
+    paper's largest planar instance, whose graph has 2,500 vertices and 12,990
+    arcs); u U{500..1500}; d U{1..20}; LF 0.9. Rows of 81,430 commodities are
+    longer than a register-resident arc kernel holds (the streamed kernels)."""
+    rp, col, nres = graphs.knn(2500, stream(seed, "graph"))
+    return random_instance(rp, col, 81430, seed, (500, 1500), (1, 20),
+                           dict(recipe="knn2500_k81430", resamples=nres, load_factor=0.9))
+
+
 RECIPES = {
     "grid4_k8": recipe_grid4_k8,
     "knn2500_k1000": recipe_knn2500_k1000,
     "grid100_k10000": recipe_grid100_k10000,
+    "knn2500_k81430": recipe_knn2500_k81430,
 }
 
 

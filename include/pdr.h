@@ -106,11 +106,12 @@ typedef struct {
                               that neighbouring arcs re-read stay in L2);
                               1 = ordinary; 2 = non-temporal. Results are the
                               same bit for bit; batches always stream. */
-    int32_t height_layout; /* work layout of the excess -> height kernel: 0 =
-                              automatic, 1 = one thread per (vertex, 16-byte
-                              vector) item, 2 = one wave per (vertex, run of
-                              64-vector chunks). Heights are the same bit for
-                              bit (tuning). */
+    int32_t batch_groups;  /* batches only: the members are split into this many
+                              groups of about equal work, each running its
+                              passes on a stream of its own (joined once per
+                              call or captured graph, not once per pass):
+                              0 = automatic (4, at most B), else 1..4. Results
+                              are the same bit for bit. */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */

@@ -186,11 +186,6 @@ void set_height_chunk(pdr_ctx *c)
         grid = 2 * kHeightGridAuto;
     c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : grid;
     c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : unroll;
-    // run-wise layout: about 8 wave items per resident wave of the 2,048-block grid
-    const int64_t nchunk = (nvec + 63) / 64;
-    const int64_t cps = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)c->n * nchunk /
-                                                                      (8 * 4 * (int64_t)kHeightGridAuto)));
-    c->g.height_run = c->req_height_layout == 2 ? (int32_t)cps : 0;
 }
 
 
@@ -415,7 +410,7 @@ void pdr_default_options(pdr_options *opt)
     opt->height_unroll = 0;
     opt->z_log_capacity = 0;
     opt->cache_policy = 0;
-    opt->height_layout = 0;
+    opt->batch_groups = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -509,8 +504,6 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         return invalid("z_log_capacity must be 0 or a power of two up to 2^20");
     if (opt.cache_policy < 0 || opt.cache_policy > 2)
         return invalid("cache_policy must be 0, 1 or 2");
-    if (opt.height_layout < 0 || opt.height_layout > 2)
-        return invalid("height_layout must be 0, 1 or 2");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
     if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
@@ -537,7 +530,6 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
     c->req_height_grid = opt.height_blocks;
     c->req_height_unroll = opt.height_unroll;
     c->req_cache_policy = opt.cache_policy;
-    c->req_height_layout = opt.height_layout;
     if (opt.z_log_capacity > 0) c->zlog_cap = opt.z_log_capacity;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
@@ -686,7 +678,7 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         PDR_UP(c->d_vinc, vinc.data(), vinc.size());
     }
 #undef PDR_UP
-    c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,      0,
+    c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,
                     c->d_row_ptr, c->d_tails, c->d_heads, c->d_in_ptr, c->d_in_idx,
                     c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
                     c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder,

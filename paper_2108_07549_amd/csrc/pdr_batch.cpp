@@ -37,18 +37,29 @@ struct pdr_batch {
     int64_t height_budget = 0;  // height blocks of a batched pass, about
     std::vector<pdr_ctx *> members;
     pdr::InstView *d_views = nullptr;
-    int2 *d_hmap = nullptr;
-    int64_t nhblocks = 0;
     struct Bucket {
         Tiling tl{1, 1};
         std::vector<int32_t> members;  // largest m * Kp first
-        int2 *d_amap = nullptr;
+        int2 *d_amap = nullptr;        // (view index within the group, block) pairs
         int64_t nblocks = 0;
         int32_t max_K = 0;
         int64_t arcs = 0;
         double ms = 0.0;  // arc-kernel time of the last tuning run
+        int32_t group = 0;
     };
     std::vector<Bucket> buckets;
+    // Members are split into groups of about equal work; the views of a group
+    // are contiguous in d_views, and each group's passes (height, objective,
+    // its buckets' arc launches) run on a stream of their own, joined once per
+    // batch of passes instead of once per pass.
+    struct Group {
+        int32_t off = 0, cnt = 0;  // views [off, off + cnt) of d_views
+        int2 *d_hmap = nullptr;    // (view index within the group, block) pairs
+        int64_t nhblocks = 0;
+    };
+    std::vector<Group> groups;
+    std::vector<int32_t> vlocal;  // member -> view index within its group
+    int32_t req_groups = 0;       // 0: automatic (kBranches, at most B)
     int32_t *d_count = nullptr;
     int32_t *h_count = nullptr;
     // arc launches of different buckets run on these streams side by side,
@@ -131,43 +142,32 @@ void drop_graph(pdr_batch *b)
     b->gexec = nullptr;
 }
 
-// Block map of one bucket: every member's arcs in blocks of arcs_per_block(L).
-std::vector<int2> bucket_map(const pdr_batch *b, const std::vector<int32_t> &mem, int lanes)
+// Block map of one bucket with `lanes` lanes per arc: every member's arcs in
+// blocks of arcs_per_block(lanes), members by their view index within the
+// bucket's group (the order of the bucket's current map).
+std::vector<int2> bucket_map(const pdr_batch *b, const pdr_batch::Bucket &bk, int lanes,
+                             const std::vector<int32_t> &local)
 {
     std::vector<int2> map;
     const int64_t apb = pdr::arcs_per_block(lanes);
-    for (int32_t i : mem) {
+    for (int32_t i : bk.members) {
         const int64_t nb = (b->members[i]->m + apb - 1) / apb;
-        for (int64_t q = 0; q < nb; ++q) map.push_back(make_int2(i, (int)q));
+        for (int64_t q = 0; q < nb; ++q) map.push_back(make_int2(local[i], (int)q));
     }
     return map;
 }
 
-// Rebuild the instance views, the height block map and the tiling buckets
-// from the members' current buffers and tilings.
+// Rebuild the instance views, the groups, their height block maps and the
+// tiling buckets from the members' current buffers and tilings.
 pdr_status build_maps(pdr_batch *b)
 {
     drop_graph(b);
     const int V = b->precision == PDR_FP64 ? 2 : 4;
     const int32_t B = b->B;
-    std::vector<pdr::InstView> views(B);
     std::vector<double> work(B);
     double W = 0.0;
     for (int32_t i = 0; i < B; ++i) {
-        pdr_ctx *c = b->members[i];
-        pdr::InstView &v = views[i];
-        v.g = c->g;
-        v.f = cur_f(c);
-        v.h = cur_h(c);
-        v.v = c->method == PDR_GDM ? cur_v(c) : nullptr;
-        v.Fsum = c->Fsum;
-        v.beta = c->beta;
-        v.prm = agd_params(c);
-        v.ctrl = c->ctrl;
-        v.zpart = c->zpart;
-        v.zlog = c->zlog;
-        v.zmask = c->zlog_cap - 1;
-        work[i] = (double)c->n * (double)(c->Kp / V);
+        work[i] = (double)b->members[i]->n * (double)(b->members[i]->Kp / V);
         W += work[i];
     }
     // members largest first: the big ones start first and the small ones fill in
@@ -177,80 +177,155 @@ pdr_status build_maps(pdr_batch *b)
         return (double)b->members[x]->m * b->members[x]->Kp >
                (double)b->members[y]->m * b->members[y]->Kp;
     });
+    // groups of about equal pass bytes (largest member to the lightest group)
+    const int G = std::max(1, std::min<int>(b->req_groups > 0 ? b->req_groups
+                                                                : pdr_batch::kBranches, B));
+    std::vector<std::vector<int32_t>> gm(G);
+    std::vector<double> load(G, 0.0);
+    for (int32_t i : order) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        gm[g].push_back(i);
+        load[g] += (double)b->members[i]->m * b->members[i]->Kp;
+    }
+    for (auto &grp : b->groups)
+        if (grp.d_hmap) (void)hipFree(grp.d_hmap);
+    b->groups.assign(G, pdr_batch::Group{});
+    std::vector<pdr::InstView> views;
+    views.reserve(B);
+    std::vector<int32_t> local(B, 0);  // member -> view index within its group
+    std::vector<int32_t> group_of(B, 0);
+    for (int g = 0; g < G; ++g) {
+        b->groups[g].off = (int32_t)views.size();
+        b->groups[g].cnt = (int32_t)gm[g].size();
+        for (int32_t i : gm[g]) {
+            pdr_ctx *c = b->members[i];
+            local[i] = (int32_t)views.size() - b->groups[g].off;
+            group_of[i] = g;
+            pdr::InstView v{};
+            v.g = c->g;
+            v.f = cur_f(c);
+            v.h = cur_h(c);
+            v.v = c->method == PDR_GDM ? cur_v(c) : nullptr;
+            v.Fsum = c->Fsum;
+            v.beta = c->beta;
+            v.prm = agd_params(c);
+            v.ctrl = c->ctrl;
+            v.zpart = c->zpart;
+            v.zlog = c->zlog;
+            v.zmask = c->zlog_cap - 1;
+            views.push_back(v);
+        }
+    }
     // about height_budget blocks in all, each member its share by work (at
     // least one block); every block grid-strides over its member's items
     const double budget = (double)b->height_budget;
-    std::vector<int2> hmap;
-    for (int32_t i : order) {
-        const int64_t need = std::max<int64_t>(1, (int64_t)std::ceil(work[i] / 256.0));
-        const int64_t share =
-            std::max<int64_t>(1, (int64_t)std::ceil(budget * work[i] / std::max(W, 1.0)));
-        const int64_t nb = std::min<int64_t>({need, share, pdr::kHeightBlocksMax});
-        views[i].nzpart = (int32_t)nb;
-        for (int64_t q = 0; q < nb; ++q) hmap.push_back(make_int2(i, (int)q));
+    for (int g = 0; g < G; ++g) {
+        std::vector<int2> hmap;
+        for (int32_t i : gm[g]) {
+            const int64_t need = std::max<int64_t>(1, (int64_t)std::ceil(work[i] / 256.0));
+            const int64_t share =
+                std::max<int64_t>(1, (int64_t)std::ceil(budget * work[i] / std::max(W, 1.0)));
+            const int64_t nb = std::min<int64_t>({need, share, pdr::kHeightBlocksMax});
+            views[b->groups[g].off + local[i]].nzpart = (int32_t)nb;
+            for (int64_t q = 0; q < nb; ++q) hmap.push_back(make_int2(local[i], (int)q));
+        }
+        PDR_BCHECK(b, upload_vec(&b->groups[g].d_hmap, hmap, b->stream));
+        b->groups[g].nhblocks = (int64_t)hmap.size();
     }
     PDR_BCHECK(b, upload_vec(&b->d_views, views, b->stream));
-    PDR_BCHECK(b, upload_vec(&b->d_hmap, hmap, b->stream));
-    b->nhblocks = (int64_t)hmap.size();
-    // tiling buckets
+    b->vlocal = local;
+    // tiling buckets, per group
     for (auto &bk : b->buckets)
         if (bk.d_amap) (void)hipFree(bk.d_amap);
     b->buckets.clear();
-    for (int32_t i : order) {
-        const Tiling tl = b->members[i]->tiling;
-        auto it = std::find_if(b->buckets.begin(), b->buckets.end(), [&](const pdr_batch::Bucket &x) {
-            return x.tl.lanes == tl.lanes && x.tl.nv == tl.nv;
-        });
-        if (it == b->buckets.end()) {
-            b->buckets.emplace_back();
-            it = b->buckets.end() - 1;
-            it->tl = tl;
+    for (int g = 0; g < G; ++g) {
+        const size_t first = b->buckets.size();
+        for (int32_t i : gm[g]) {
+            const Tiling tl = b->members[i]->tiling;
+            auto it = std::find_if(b->buckets.begin() + first, b->buckets.end(),
+                                   [&](const pdr_batch::Bucket &x) {
+                                       return x.tl.lanes == tl.lanes && x.tl.nv == tl.nv;
+                                   });
+            if (it == b->buckets.end()) {
+                b->buckets.emplace_back();
+                it = b->buckets.end() - 1;
+                it->tl = tl;
+                it->group = g;
+            }
+            it->members.push_back(i);
+            it->max_K = std::max(it->max_K, b->members[i]->K);
+            it->arcs += b->members[i]->m;
         }
-        it->members.push_back(i);
-        it->max_K = std::max(it->max_K, b->members[i]->K);
-        it->arcs += b->members[i]->m;
     }
     for (auto &bk : b->buckets) {
-        const std::vector<int2> map = bucket_map(b, bk.members, bk.tl.lanes);
+        std::vector<int2> map;
+        const int64_t apb = pdr::arcs_per_block(bk.tl.lanes);
+        for (int32_t i : bk.members) {
+            const int64_t nb = (b->members[i]->m + apb - 1) / apb;
+            for (int64_t q = 0; q < nb; ++q) map.push_back(make_int2(local[i], (int)q));
+        }
         PDR_BCHECK(b, upload_vec(&bk.d_amap, map, b->stream));
         bk.nblocks = (int64_t)map.size();
     }
     return PDR_OK;
 }
 
-// The bucket arc launches of one pass, forked over the branch streams `aux`
-// (largest bucket first, round robin) and joined back to st.
-hipError_t enqueue_batch_arcs(pdr_batch *b, hipStream_t st, hipStream_t *aux)
-{
-    const bool fp64 = b->precision == PDR_FP64;
-    const int nbr = (int)std::min<size_t>(pdr_batch::kBranches, b->buckets.size());
-    hipError_t e = hipSuccess;
-    if (nbr > 1) e = hipEventRecord(b->fork, st);
-    for (int r = 1; r < nbr && e == hipSuccess; ++r) e = hipStreamWaitEvent(aux[r], b->fork, 0);
-    for (size_t k = 0; k < b->buckets.size() && e == hipSuccess; ++k) {
-        const auto &bk = b->buckets[k];
-        hipStream_t s_k = nbr > 1 && k % nbr != 0 ? aux[k % nbr] : st;
-        e = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl, s_k);
-    }
-    for (int r = 1; r < nbr && e == hipSuccess; ++r) {
-        e = hipEventRecord(b->join[r], aux[r]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[r], 0);
-    }
-    return e;
-}
+// Views of a group, and of a bucket's group.
+const pdr::InstView *group_views(const pdr_batch *b, int g) { return b->d_views + b->groups[g].off; }
 
-// `count` batched passes on st: the height launch (objective and stop test
-// included), then the arc launches.
-hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st, hipStream_t *aux)
+// The height and objective launches of every group, one after another on st.
+hipError_t enqueue_heights(pdr_batch *b, hipStream_t st)
 {
     const bool fp64 = b->precision == PDR_FP64;
-    for (int64_t q = 0; q < count; ++q) {
-        hipError_t e = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
-                                           b->height_unroll, st);
-        if (e == hipSuccess) e = enqueue_batch_arcs(b, st, aux);
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        const auto &grp = b->groups[g];
+        hipError_t e = pdr::launch_bheight(group_views(b, (int)g), grp.cnt, grp.d_hmap,
+                                           grp.nhblocks, fp64, b->height_unroll, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// The arc launches of one pass of every group, one after another on st.
+hipError_t enqueue_batch_arcs(pdr_batch *b, hipStream_t st)
+{
+    const bool fp64 = b->precision == PDR_FP64;
+    for (const auto &bk : b->buckets) {
+        hipError_t e = pdr::launch_barc(b->method, group_views(b, bk.group), bk.d_amap,
+                                        bk.nblocks, fp64, bk.tl, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// `count` batched passes: each group's height launch (objective and stop test
+// included) and arc launches on a stream of its own (group 0 on st, group g on
+// aux[g]), forked from st at the start and joined back at the end.
+hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st, hipStream_t *aux)
+{
+    const bool fp64 = b->precision == PDR_FP64;
+    const int G = (int)b->groups.size();
+    hipError_t e = hipSuccess;
+    if (G > 1) e = hipEventRecord(b->fork, st);
+    for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(aux[g], b->fork, 0);
+    for (int64_t q = 0; q < count && e == hipSuccess; ++q)
+        for (int g = 0; g < G && e == hipSuccess; ++g) {
+            hipStream_t sg = g == 0 ? st : aux[g];
+            const auto &grp = b->groups[g];
+            e = pdr::launch_bheight(group_views(b, g), grp.cnt, grp.d_hmap, grp.nhblocks, fp64,
+                                    b->height_unroll, sg);
+            for (size_t k = 0; k < b->buckets.size() && e == hipSuccess; ++k) {
+                const auto &bk = b->buckets[k];
+                if (bk.group == g)
+                    e = pdr::launch_barc(b->method, group_views(b, g), bk.d_amap, bk.nblocks,
+                                         fp64, bk.tl, sg);
+            }
+        }
+    for (int g = 1; g < G && e == hipSuccess; ++g) {
+        e = hipEventRecord(b->join[g], aux[g]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[g], 0);
+    }
+    return e;
 }
 
 pdr_status batch_graph(pdr_batch *b, hipGraphExec_t *out)
@@ -291,6 +366,9 @@ void batch_free(pdr_batch *b)
     for (auto &bk : b->buckets)
         if (bk.d_amap) (void)hipFree(bk.d_amap);
     b->buckets.clear();
+    for (auto &grp : b->groups)
+        if (grp.d_hmap) (void)hipFree(grp.d_hmap);
+    b->groups.clear();
     for (pdr_ctx *c : b->members) {
         if (!c) continue;
         c->batch_member = false;
@@ -298,11 +376,9 @@ void batch_free(pdr_batch *b)
     }
     b->members.clear();
     if (b->d_views) (void)hipFree(b->d_views);
-    if (b->d_hmap) (void)hipFree(b->d_hmap);
     if (b->d_count) (void)hipFree(b->d_count);
     if (b->h_count) (void)hipHostFree(b->h_count);
     b->d_views = nullptr;
-    b->d_hmap = nullptr;
     b->d_count = nullptr;
     b->h_count = nullptr;
     for (auto &x : b->cap_aux)
@@ -414,6 +490,10 @@ static pdr_status pdr_batch_init_body(pdr_batch **out, int32_t B, const pdr_inst
         g_init_error = "height_blocks of a batch must be 0 or 1..2^20";
         return PDR_ERR_INVALID;
     }
+    if (opt.batch_groups < 0 || opt.batch_groups > pdr_batch::kBranches) {
+        g_init_error = "batch_groups must be 0..4";
+        return PDR_ERR_INVALID;
+    }
     auto *b = new pdr_batch();
     *created = b;
     b->B = B;
@@ -422,6 +502,7 @@ static pdr_status pdr_batch_init_body(pdr_batch **out, int32_t B, const pdr_inst
     b->graph_sweeps = opt.graph_sweeps == 0 ? 32 : (opt.graph_sweeps < 0 ? 0 : opt.graph_sweeps);
     b->height_unroll = opt.height_unroll > 0 ? opt.height_unroll : kHeightUnrollAuto;
     b->height_budget = opt.height_blocks > 0 ? opt.height_blocks : kBatchHeightBlocks;
+    b->req_groups = opt.batch_groups;
     auto init_fail_b = [&](pdr_status st, const std::string &msg) {
         g_init_error = msg;
         batch_free(b);
@@ -565,8 +646,8 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
     PDR_BCHECK(b, snapshot_members(b, sn, all, true));
     // heights of the current flows, so the arc kernels see the real workload
     PDR_BCHECK(b, pdr::launch_bbegin(b->d_views, b->B, 0.0, 0.0, b->stream));
-    PDR_BCHECK(b, pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
-                                      b->height_unroll, b->stream));
+    PDR_BCHECK(b, enqueue_heights(b, b->stream));
+    const int32_t start_groups = b->req_groups;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PDR_BCHECK(b, hipEventCreate(&e0));
     PDR_BCHECK(b, hipEventCreate(&e1));
@@ -593,20 +674,20 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
                     (int64_t)L * nv > cap)
                     continue;
                 const Tiling tl{L, nv};
-                const std::vector<int2> map = bucket_map(b, bk.members, L);
+                const std::vector<int2> map = bucket_map(b, bk, L, b->vlocal);
                 err = upload_vec(&amap, map, b->stream);
                 if (err != hipSuccess) break;
                 // the same starting state for every candidate (only this
                 // bucket's members change; the heights stay those computed above)
                 err = restore_members(b, sn, bk.members);
                 if (err == hipSuccess)
-                    err = pdr::launch_barc(b->method, b->d_views, amap, (int64_t)map.size(), fp64,
-                                           tl, b->stream);
+                    err = pdr::launch_barc(b->method, group_views(b, bk.group), amap,
+                                           (int64_t)map.size(), fp64, tl, b->stream);
                 if (err == hipSuccess) err = restore_members(b, sn, bk.members);
                 if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
                 for (int r = 0; r < reps && err == hipSuccess; ++r)
-                    err = pdr::launch_barc(b->method, b->d_views, amap, (int64_t)map.size(),
-                                           fp64, tl, b->stream);
+                    err = pdr::launch_barc(b->method, group_views(b, bk.group), amap,
+                                           (int64_t)map.size(), fp64, tl, b->stream);
                 if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
                 if (err == hipSuccess) err = hipEventSynchronize(e1);
                 float ms = 0.0f;
@@ -630,12 +711,9 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
         b->height_budget = cand;
         st = build_maps(b);
         if (st != PDR_OK) return bail(st);
-        err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
-                                  b->height_unroll, b->stream);
+        err = enqueue_heights(b, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
-        for (int r = 0; r < reps && err == hipSuccess; ++r)
-            err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
-                                      b->height_unroll, b->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = enqueue_heights(b, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -649,9 +727,10 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
     // the height launch. Time whole passes (from the saved state, stop tests
     // off) with the tuned and with the starting configuration and keep the
     // faster.
-    auto apply = [&](const std::vector<Tiling> &tl, int64_t budget) -> pdr_status {
+    auto apply = [&](const std::vector<Tiling> &tl, int64_t budget, int32_t groups) -> pdr_status {
         for (int32_t i = 0; i < b->B; ++i) b->members[i]->tiling = tl[i];
         b->height_budget = budget;
+        b->req_groups = groups;
         return build_maps(b);
     };
     auto time_passes = [&](double *ms_out) -> hipError_t {
@@ -667,20 +746,28 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
         *ms_out = (double)ms / reps;
         return e;
     };
-    double t_tuned = 0.0, t_start = 0.0;
-    if (err == hipSuccess) {
-        st = apply(member_tl, best_budget);
+    // candidates: the tuned tilings and height blocks with the members in one
+    // group and in kBranches groups, and the starting configuration
+    struct Cand {
+        const std::vector<Tiling> *tl;
+        int64_t budget;
+        int32_t groups;
+        double ms;
+    };
+    std::vector<Cand> cands = {{&member_tl, best_budget, pdr_batch::kBranches, 0.0},
+                               {&member_tl, best_budget, 1, 0.0},
+                               {&start_tl, start_budget, start_groups, 0.0}};
+    for (size_t q = 0; q < cands.size() && err == hipSuccess; ++q) {
+        st = apply(*cands[q].tl, cands[q].budget, cands[q].groups);
         if (st != PDR_OK) return bail(st);
-        err = time_passes(&t_tuned);
+        err = time_passes(&cands[q].ms);
     }
     if (err == hipSuccess) {
-        st = apply(start_tl, start_budget);
-        if (st != PDR_OK) return bail(st);
-        err = time_passes(&t_start);
-    }
-    const bool keep_tuned = err == hipSuccess && t_tuned < t_start;
-    if (err == hipSuccess && keep_tuned) {
-        st = apply(member_tl, best_budget);
+        // the fastest stays; the starting configuration unless another beats it
+        size_t pick = cands.size() - 1;
+        for (size_t q = 0; q + 1 < cands.size(); ++q)
+            if (cands[q].ms < cands[pick].ms) pick = q;
+        st = apply(*cands[pick].tl, cands[pick].budget, cands[pick].groups);
         if (st != PDR_OK) return bail(st);
     }
     // each final bucket's arc launch on the saved state, for pdr_batch_buckets
@@ -689,8 +776,8 @@ static pdr_status pdr_batch_tune_body(pdr_batch *b, int32_t reps, int64_t *heigh
         err = restore_members(b, sn, bk.members);
         if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
         for (int r = 0; r < reps && err == hipSuccess; ++r)
-            err = pdr::launch_barc(b->method, b->d_views, bk.d_amap, bk.nblocks, fp64, bk.tl,
-                                   b->stream);
+            err = pdr::launch_barc(b->method, group_views(b, bk.group), bk.d_amap, bk.nblocks,
+                                   fp64, bk.tl, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -710,18 +797,15 @@ static pdr_status pdr_batch_profile_sweeps_body(pdr_batch *b, int64_t sweeps, do
     pdr_status st;
     if (!busable(b, &st)) return st;
     if (sweeps < 0 || !kernel_ms) return bfail(b, PDR_ERR_INVALID, "bad arguments");
-    const bool fp64 = b->precision == PDR_FP64;
     hipEvent_t ev[3];
     for (auto &x : ev) PDR_BCHECK(b, hipEventCreate(&x));
     double tot[2] = {0.0, 0.0};
     hipError_t err = pdr::launch_bbegin(b->d_views, b->B, 0.0, 0.0, b->stream);
     for (int64_t s0 = 0; s0 < sweeps && err == hipSuccess; ++s0) {
         err = hipEventRecord(ev[0], b->stream);
-        if (err == hipSuccess)
-            err = pdr::launch_bheight(b->d_views, b->B, b->d_hmap, b->nhblocks, fp64,
-                                      b->height_unroll, b->stream);
+        if (err == hipSuccess) err = enqueue_heights(b, b->stream);
         if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
-        if (err == hipSuccess) err = enqueue_batch_arcs(b, b->stream, b->aux);
+        if (err == hipSuccess) err = enqueue_batch_arcs(b, b->stream);
         if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
         if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
         for (int r = 0; r < 2 && err == hipSuccess; ++r) {

@@ -62,7 +62,6 @@ struct pdr_ctx {
     int32_t req_height_grid = 0;           // 0 = automatic
     int32_t req_height_unroll = 0;         // 0 = automatic
     int32_t req_cache_policy = 0;          // 0 = automatic, 1 = ordinary, 2 = non-temporal
-    int32_t req_height_layout = 0;         // 0 = automatic, 1 = item-wise, 2 = run-wise
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;

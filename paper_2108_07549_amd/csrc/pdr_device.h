@@ -387,173 +387,6 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
     }
 }
 
-// Excess -> height with one wave per (vertex, run of commodity chunks): the
-// wave reads the vertex's record and its first kRunRows incidence entries
-// once, then walks its run of 64-vector chunks, each lane summing one 16-byte
-// vector of every incident row. The row loads of one chunk depend only on
-// those entries, so a wave keeps kRunRows loads in flight from chunk to chunk
-// instead of re-reading the record and the incidence list before every chunk.
-// Work items (run, vertex position) are run-major: the waves in flight cover
-// the same chunks of a window of consecutive vertices, so both reads of an
-// arc's chunk fall close together in time. Each element is summed in the same
-// order as height_core (in-arcs, then out-arcs, then injections), so the
-// heights are the same bit for bit.
-constexpr int kRunRows = 8;
-
-template <typename T, bool RESID, bool NT = true>
-__device__ __forceinline__ void height_core_run(const DevGraph &g, const T *__restrict__ f,
-                                                T *__restrict__ h, double *__restrict__ h64,
-                                                double *__restrict__ zpart,
-                                                double *__restrict__ maxpart,
-                                                const double *__restrict__ Fsum, int64_t blk,
-                                                int64_t nblk, int64_t part)
-{
-    constexpr int V = VecT<T>::N;
-    constexpr int U = kRunRows;
-    constexpr bool kNoise = !RESID && sizeof(T) == 4;
-    __shared__ double sh[12];
-    const int lane = (int)threadIdx.x & 63;
-    const int wv = (int)threadIdx.x >> 6;
-    const int nvec = g.Kp / V;
-    const int64_t Kp = g.Kp;
-    const int nchunk = (nvec + 63) / 64;
-    const int cps = g.height_run;
-    const int nrun = (nchunk + cps - 1) / cps;
-    const int64_t witems = (int64_t)nrun * g.n;
-    double zs = 0.0, mx = 0.0, ns = 0.0;
-    for (int64_t wi = blk * 4 + wv; wi < witems; wi += nblk * 4) {
-        const int s = (int)(wi / g.n);
-        const int pos = (int)(wi - (int64_t)s * g.n);
-        const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
-        const int4 vj = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
-        const int i = vi.x, p0 = vi.y, pin = vi.y + vi.z, p1 = vi.w;
-        const int dg = p1 - p0;
-        int e[U];
-#pragma unroll
-        for (int b = 0; b < U; ++b) e[b] = p0 + b < p1 ? g.vinc[p0 + b] : -1;
-        const int c0 = s * cps;
-        const int c1 = c0 + cps < nchunk ? c0 + cps : nchunk;
-        for (int c = c0; c < c1; ++c) {
-            const int q = c * 64 + lane;
-            if (q >= nvec) break;
-            const int k0 = q * V;
-            double acc[V];
-            float mag[V];
-#pragma unroll
-            for (int w = 0; w < V; ++w) {
-                acc[w] = 0.0;
-                mag[w] = 0.0f;
-            }
-            T x[U][V];
-#pragma unroll
-            for (int b = 0; b < U; ++b)
-                if (e[b] >= 0) load_vec(f + (int64_t)e[b] * Kp + k0, x[b]);
-#pragma unroll
-            for (int b = 0; b < U; ++b)
-                if (e[b] >= 0) {
-                    const double sg = p0 + b < pin ? 1.0 : -1.0;
-#pragma unroll
-                    for (int w = 0; w < V; ++w) {
-                        acc[w] += sg * (double)x[b][w];
-                        if constexpr (kNoise) mag[w] += fabsf((float)x[b][w]);
-                    }
-                }
-            // incident rows beyond the first U, in batches of U
-            for (int p = p0 + U; p < p1; p += U) {
-                int e2[U];
-#pragma unroll
-                for (int b = 0; b < U; ++b) e2[b] = g.vinc[p + b < p1 ? p + b : p];
-                T y[U][V];
-#pragma unroll
-                for (int b = 0; b < U; ++b) load_vec(f + (int64_t)e2[b] * Kp + k0, y[b]);
-#pragma unroll
-                for (int b = 0; b < U; ++b)
-                    if (p + b < p1) {
-                        const double sg = p + b < pin ? 1.0 : -1.0;
-#pragma unroll
-                        for (int w = 0; w < V; ++w) {
-                            acc[w] += sg * (double)y[b][w];
-                            if constexpr (kNoise) mag[w] += fabsf((float)y[b][w]);
-                        }
-                    }
-            }
-            if (k0 <= vj.w && k0 + V > vj.z) {
-                for (int p = vj.x; p < vj.y; ++p) {
-                    const int k = g.inj_k[p] - k0;
-                    const double val = g.inj_val[p];
-#pragma unroll
-                    for (int w = 0; w < V; ++w)
-                        if (w == k) {
-                            acc[w] += val;
-                            if constexpr (kNoise) mag[w] += (float)fabs(val);
-                        }
-                }
-            }
-            T hv[V];
-            double hd[V];
-#pragma unroll
-            for (int w = 0; w < V; ++w) {
-                const double hh = dg > 0 ? acc[w] / (double)dg : 0.0;
-                hd[w] = hh;
-                hv[w] = (T)hh;
-                zs += acc[w] * hh;
-                if (RESID) mx = fmax(mx, fabs(acc[w]));
-                if constexpr (kNoise) {
-                    const double r = kFp32Unit * (double)mag[w];
-                    if (dg > 0) ns += r * r / (double)dg;
-                }
-            }
-            if constexpr (RESID) {
-                double *dst = h64 + (int64_t)i * Kp + k0;
-#pragma unroll
-                for (int w = 0; w < V; w += 2)
-                    *reinterpret_cast<double2 *>(dst + w) = make_double2(hd[w], hd[w + 1]);
-            } else {
-                store_vec_s<NT>(h + (int64_t)i * Kp + k0, hv);
-            }
-        }
-    }
-    double ps = 0.0;
-    if constexpr (!RESID) {
-        for (int64_t e = part * 256 + threadIdx.x; e < g.m; e += nblk * 256) {
-            const double over = Fsum[e] - g.u[e];
-            if (over > 0.0) ps += over * over;
-        }
-    }
-    zs = wave_sum(zs);
-    if (RESID) mx = wave_max(mx);
-    else ps = wave_sum(ps);
-    if constexpr (kNoise) ns = wave_sum(ns);
-    if (lane == 0) {
-        sh[wv] = zs;
-        sh[4 + wv] = RESID ? mx : ps;
-        sh[8 + wv] = ns;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        zpart[part] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-        if (RESID) {
-            maxpart[part] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
-        } else {
-            zpart[nblk + part] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
-            zpart[2 * nblk + part] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
-        }
-    }
-}
-
-template <typename T, bool RESID, bool NT>
-__global__ __launch_bounds__(256) void k_height_run(DevGraph g, const T *__restrict__ f,
-                                                    T *__restrict__ h, double *__restrict__ h64,
-                                                    double *__restrict__ zpart,
-                                                    double *__restrict__ maxpart,
-                                                    const double *__restrict__ Fsum,
-                                                    const Ctrl *__restrict__ ctrl)
-{
-    if (!RESID && ctrl->stopped) return;
-    height_core_run<T, RESID, NT>(g, f, h, h64, zpart, maxpart, Fsum,
-                                  xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
-}
-
 // Eight waves per SIMD (at most 64 VGPRs) for the unrolls up to 4, so that the
 // default grid (8 blocks of 4 waves on each of the 256 CUs) is resident at
 // once and no block starts late.

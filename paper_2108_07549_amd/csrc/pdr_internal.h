@@ -34,8 +34,6 @@ struct DevGraph {
     int32_t height_cv;       // vectors per commodity chunk in the height kernel
     int32_t height_grid;     // blocks of the height kernel (<= kHeightBlocksMax)
     int32_t height_unroll;   // incident rows loaded together per thread (1, 2 or 4)
-    int32_t height_run;      // > 0: the run-wise height kernel (k_height_run) with
-                             // this many 64-vector chunks per wave item; 0: k_height
     const int32_t *row_ptr;  // n+1: out-arcs of i are [row_ptr[i], row_ptr[i+1])
     const int32_t *tails;    // m
     const int32_t *heads;    // m

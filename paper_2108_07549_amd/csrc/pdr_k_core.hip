@@ -121,11 +121,7 @@ __global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src,
 int64_t height_blocks(const DevGraph &g, int elem_bytes)
 {
     const int V = 16 / elem_bytes;
-    int64_t work = (int64_t)g.n * (g.Kp / V);
-    if (g.height_run > 0) {  // wave items of the run-wise kernel, 4 per block
-        const int64_t nchunk = (g.Kp / V + 63) / 64;
-        work = (int64_t)g.n * ((nchunk + g.height_run - 1) / g.height_run) * 64;
-    }
+    const int64_t work = (int64_t)g.n * (g.Kp / V);
     int64_t b = work > 0 ? (work + 255) / 256 : 1;
     const int64_t cap = g.height_grid > 0 ? g.height_grid : kHeightBlocksMax;
     return b < cap ? b : cap;
@@ -141,14 +137,7 @@ template <typename T, int U>
 static void height_launch(const DevGraph &g, const T *f, T *h, double *zpart, const double *Fsum,
                           Ctrl *ctrl, unsigned nb, hipStream_t st)
 {
-    if (g.height_run > 0) {
-        if (g.temporal)
-            k_height_run<T, false, false><<<nb, 256, 0, st>>>(g, f, h, nullptr, zpart, nullptr,
-                                                             Fsum, ctrl);
-        else
-            k_height_run<T, false, true><<<nb, 256, 0, st>>>(g, f, h, nullptr, zpart, nullptr,
-                                                            Fsum, ctrl);
-    } else if (g.temporal)
+    if (g.temporal)
         k_height<T, false, U, false><<<nb, 256, 0, st>>>(g, f, h, nullptr, zpart, nullptr, Fsum,
                                                          ctrl);
     else
@@ -184,13 +173,7 @@ hipError_t launch_height_resid(const DevGraph &g, bool fp64, const void *f, doub
                                double *zpart, double *maxpart, hipStream_t st)
 {
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
-    if (g.height_run > 0 && fp64)
-        k_height_run<double, true, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64,
-                                                            zpart, maxpart, nullptr, nullptr);
-    else if (g.height_run > 0)
-        k_height_run<float, true, true><<<nb, 256, 0, st>>>(g, (const float *)f, nullptr, h64,
-                                                           zpart, maxpart, nullptr, nullptr);
-    else if (fp64)
+    if (fp64)
         k_height<double, true, 4, true><<<nb, 256, 0, st>>>(g, (const double *)f, nullptr, h64, zpart,
                                                       maxpart, nullptr, nullptr);
     else

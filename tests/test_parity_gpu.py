@@ -740,26 +740,3 @@ def test_solve_split_into_calls_equals_one_call(method):
     say("solve split", method, one, (n32, n64))
     assert one[1] > 0 and (n32, n64) == one
     assert np.array_equal(f_one, f_many) and r_one["z"] == r_many["z"]
-
-
-@pytest.mark.parametrize("precision", [pdr.FP64, pdr.FP32_BULK])
-@pytest.mark.parametrize("method", ["eso", "gdm"])
-def test_height_layouts_give_the_same_iterates(method, precision):
-    """The item-wise and the run-wise excess -> height kernels sum every
-    element in the same order: flows and heights are equal bit for bit (the
-    objective's partial sums are grouped differently, so z agrees to rounding),
-    for rows shorter than one chunk, ragged rows and rows of many chunks."""
-    gm, _ = METHODS[method]
-    cases = [recipe_small("knn", 200, 37, seed=9, u_range=(5, 40), d_range=(1, 6)),
-             recipe_small("grid", 9, 1000, seed=10, u_range=(20, 200), d_range=(1, 5)),
-             recipe_small("knn", 60, 3001, seed=11, u_range=(50, 900), d_range=(1, 5))]
-    for inst in cases:
-        out = []
-        for layout in (1, 2):
-            with ctx_for(inst, gm, precision, height_layout=layout) as c:
-                c.sweep(30)
-                out.append((c.flows(), c.heights(), c.z_log(0, 30)))
-        say("height layouts", method, precision, inst.meta.get("recipe"))
-        assert np.array_equal(out[0][0], out[1][0])
-        assert np.array_equal(out[0][1], out[1][1])
-        assert np.allclose(out[0][2], out[1][2], rtol=1e-12, atol=0)
