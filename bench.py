@@ -179,7 +179,9 @@ def time_to_target(pdr, inst, method, precision, target, cap, window=512, chunk=
             if zl[-1] > 0 and zl[0] > zl[-1]:
                 rate = np.log(zl[0] / zl[-1]) / (len(zl) - 1)
                 more = float(np.log(zl[-1] / target) / rate)
-                per_pass = sec / max(n32 + n64, 1)
+                # further passes cost what the last call's passes cost (an FP32
+                # run that has handed over continues in FP64)
+                per_pass = (sec - prev_sec) / max(a + b, 1)
                 out["extrapolation"] = dict(
                     kind="extrapolated from the descent rate of the last "
                          f"{len(zl) - 1} passes; not measured",
@@ -233,10 +235,13 @@ def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
                 certified=cert, generate_s=gen_s, init_s=init_s, auto=auto, tuned=after)
 
 
-def batch_verdicts(pdr, insts, method, seconds, chunk=2000):
-    """The batch swept in FP64 for about `seconds` of wall time; every member's
-    verdict (Farkas gap > tau: infeasible; z <= 1e-8: feasible) against its
-    certified label (gen.batch: column-generation brackets)."""
+def batch_verdicts(pdr, insts, method, seconds, members=96, chunk=5000):
+    """The `members` members of least work (m K) of the batch swept together in
+    FP64 for about `seconds` of wall time; every member's verdict (Farkas gap >
+    tau: infeasible; z <= 1e-8: feasible) against its certified label
+    (gen.batch: column-generation brackets)."""
+    order = sorted(range(len(insts)), key=lambda q: insts[q].m * insts[q].K)[:members]
+    insts = [insts[q] for q in sorted(order)]
     with pdr.Batch(insts, method=method, precision=pdr.FP64) as b:
         t0 = time.perf_counter()
         passes = 0
@@ -247,8 +252,8 @@ def batch_verdicts(pdr, insts, method, seconds, chunk=2000):
             if time.perf_counter() - t0 >= seconds:
                 break
         sec = time.perf_counter() - t0
-        out = dict(passes=passes, seconds=sec, decided=0, agree=0, disagree=0, undecided=0,
-                   by_label={})
+        out = dict(members=len(insts), passes=passes, seconds=sec, decided=0, agree=0,
+                   disagree=0, undecided=0, by_label={})
         for q, inst in enumerate(insts):
             v = b.member(q).residual()["verdict"]
             lab = inst.meta.get("certified", "uncertified")
@@ -378,8 +383,9 @@ def main():
                     help="skip the adjoint (reverse-mode gradient) timing")
     ap.add_argument("--no-long-rows", action="store_true",
                     help="skip the K = 81,430 (streamed rows) workload")
-    ap.add_argument("--verdict-seconds", type=float, default=30.0,
-                    help="wall time of the batch verdict run (0: skip)")
+    ap.add_argument("--verdict-seconds", type=float, default=60.0,
+                    help="wall time of the batch verdict run on the 96 members of least "
+                         "work (0: skip)")
     ap.add_argument("--ttr-budget", type=float, default=6.0,
                     help="seconds per variant of the time-to-residual ladder (0: skip)")
     ap.add_argument("--ttr-workload", default="knn2500_k1000",
