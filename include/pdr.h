@@ -89,7 +89,7 @@ typedef struct {
     int32_t graph_sweeps;  /* passes per captured HIP graph in pdr_sweep: 0 = 32,
                               < 0 = launch every kernel directly */
     int32_t height_chunk;  /* 16-byte vectors per commodity chunk in the height
-                              kernel: 0 = automatic, else a power of two 1..256 */
+                              kernel: 0 = automatic, else a power of two 1..65536 */
     int32_t cluster_size;  /* vertices per locality cluster of the visiting order:
                               0 = automatic (64), 1 = the caller's vertex order */
     int32_t height_blocks; /* blocks of the grid-stride height kernel: 0 = automatic,

@@ -506,9 +506,9 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         return invalid("cache_policy must be 0, 1 or 2");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
-    if (opt.height_chunk < 0 || opt.height_chunk > 256 ||
+    if (opt.height_chunk < 0 || opt.height_chunk > 65536 ||
         (opt.height_chunk & (opt.height_chunk - 1)) != 0)
-        return invalid("height_chunk must be 0 or a power of two up to 256");
+        return invalid("height_chunk must be 0 or a power of two up to 65536");
 
     pdr_ctx *c = new pdr_ctx();
     *created = c;

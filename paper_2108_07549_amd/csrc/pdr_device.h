@@ -321,9 +321,17 @@ __device__ __forceinline__ void height_core(const DevGraph &g, const T *__restri
                 }
         }
         // injections (hatDelta) of this vertex that fall in the vector's
-        // commodities [k0, k0 + V)
+        // commodities [k0, k0 + V): the vertex's list is sorted by commodity,
+        // so a binary search finds the first one (a vertex with many
+        // commodities would otherwise scan its whole list for every vector)
         if (k0 <= vj.w && k0 + V > vj.z) {
-            for (int p = vj.x; p < vj.y; ++p) {
+            int lo = vj.x, hi = vj.y;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (g.inj_k[mid] < k0) lo = mid + 1;
+                else hi = mid;
+            }
+            for (int p = lo; p < vj.y && g.inj_k[p] < k0 + V; ++p) {
                 const int k = g.inj_k[p] - k0;
                 const double val = g.inj_val[p];
 #pragma unroll

@@ -41,7 +41,7 @@ struct DevGraph {
     const int32_t *in_idx;   // m, ascending arc ids per head
     const int32_t *deg;      // n: in-degree + out-degree
     const int32_t *inj_ptr;  // n+1: injections of vertex i
-    const int32_t *inj_k;    // 2K: commodity of each injection
+    const int32_t *inj_k;    // 2K: commodity of each injection, ascending per vertex
     const double *inj_val;   // 2K: +d_k at s_k, -d_k at t_k
     const double *u;         // m capacities
     const int32_t *s, *t;    // K
