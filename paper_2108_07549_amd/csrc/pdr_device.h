@@ -854,11 +854,11 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
 // kStreamMinVectors 16-byte vectors): one block of kStreamLanes lanes per
 // arc streams the row in tiles of kStreamLanes x TV vectors and recomputes
 // the row's values from f, h_i and h_j on every pass over it, with the same
-// per-element arithmetic as the resident kernels. PDR-ESO needs one pass for
-// the first sums, one per step of the threshold iteration and one for the
-// update; PDR-AGD and PDR-GDM one for their sums and one for the update (if
-// accepted). Loads are ordinary (the passes re-read the row); the final
-// stores are streaming.
+// per-element arithmetic as the resident kernels. PDR-ESO needs one pass
+// (reading f, h_i, h_j and writing f) for an arc within capacity, and for a
+// congested one also a pass over its own row per step of the threshold
+// iteration and one for the update; PDR-AGD and PDR-GDM one pass for their
+// sums and one for the update (if accepted). Stores are streaming.
 constexpr int kStreamLanes = 1024;
 // vectors per lane of one tile; Tiling{kStreamLanes, -kStreamTile} names the
 // streamed arc kernels
@@ -877,6 +877,12 @@ __device__ __forceinline__ void stream_c(const T *__restrict__ fe, const T *__re
     for (int w = 0; w < V; ++w) c[w] = (T)0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
 }
 
+// The first pass also stores max(c, 0) in place of the row. Every later step
+// needs only that: the threshold th = max(theta, half) is never negative, so
+// c > th exactly where the stored value exceeds th, and max(c - half, 0) equals
+// max(stored - half, 0) (an entry with c <= 0 ends at zero either way). An
+// arc whose positive sum stays within its capacity (half = 0) is then done
+// after one pass; a congested one re-reads only its own row.
 template <typename T, int TV, bool CAP>
 __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict__ f,
                                                const T *__restrict__ h, double *__restrict__ Fsum,
@@ -897,48 +903,55 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T c[V];
+                T c[V], o[V];
                 stream_c(fe, hi, hj, q, c);
 #pragma unroll
-                for (int w = 0; w < V; ++w)
+                for (int w = 0; w < V; ++w) {
+                    o[w] = c[w] > (T)0 ? c[w] : (T)0;
                     if (c[w] > (T)0) {
                         red[0] += (double)c[w];
                         red[1] += 1.0;
                     }
+                }
+                store_vec_s<true>(fe + q * V, o);
             }
         }
     group_sum<L, 2>(red, lds, phase);
     double Ssum = red[0], P = red[1];
+    if (Ssum <= u) {
+        // half = 0: the stored row is the new row and its sum is Ssum (the
+        // same terms summed in the same order)
+        if (lane == 0) Fsum[e] = Ssum;
+        return;
+    }
     double half = 0.0;
-    if (Ssum > u) {
-        double theta = 0.0;
-        for (;;) {
-            half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
-            const double th = fmax(theta, half);
-            double r2[2] = {0.0, 0.0};
-            for (int base = 0; base < nvec; base += L * TV)
+    double theta = 0.0;
+    for (;;) {
+        half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
+        const double th = fmax(theta, half);
+        double r2[2] = {0.0, 0.0};
+        for (int base = 0; base < nvec; base += L * TV)
 #pragma unroll
-                for (int v = 0; v < TV; ++v) {
-                    const int q = base + v * L + lane;
-                    if (q < nvec) {
-                        T c[V];
-                        stream_c(fe, hi, hj, q, c);
+            for (int v = 0; v < TV; ++v) {
+                const int q = base + v * L + lane;
+                if (q < nvec) {
+                    T x[V];
+                    load_vec(fe + q * V, x);
 #pragma unroll
-                        for (int w = 0; w < V; ++w) {
-                            const double cc = (double)c[w];
-                            if (cc > th) {
-                                r2[0] += cc;
-                                r2[1] += 1.0;
-                            }
+                    for (int w = 0; w < V; ++w) {
+                        const double cc = (double)x[w];
+                        if (cc > th) {
+                            r2[0] += cc;
+                            r2[1] += 1.0;
                         }
                     }
                 }
-            group_sum<L, 2>(r2, lds, phase);
-            if (r2[1] == P || (CAP && r2[1] == 0.0)) break;
-            Ssum = r2[0];
-            P = r2[1];
-            theta = th;
-        }
+            }
+        group_sum<L, 2>(r2, lds, phase);
+        if (r2[1] == P || (CAP && r2[1] == 0.0)) break;
+        Ssum = r2[0];
+        P = r2[1];
+        theta = th;
     }
     double fs[1] = {0.0};
     for (int base = 0; base < nvec; base += L * TV)
@@ -946,11 +959,11 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T c[V], o[V];
-                stream_c(fe, hi, hj, q, c);
+                T x[V], o[V];
+                load_vec(fe + q * V, x);
 #pragma unroll
                 for (int w = 0; w < V; ++w) {
-                    const double val = (double)c[w] - half;
+                    const double val = (double)x[w] - half;
                     o[w] = (T)(val > 0.0 ? val : 0.0);
                     fs[0] += (double)o[w];
                 }
