@@ -61,9 +61,9 @@ def measured_traffic(key: str):
     return entry.get("bytes_per_launch")
 
 
-def time_variant(pdr, inst, method, precision, steps, warmup):
+def time_variant(pdr, inst, method, precision, steps, warmup, **opts):
     """Warm up, then time exactly `steps` sweeps; returns timing and per-kernel ms."""
-    ctx = pdr.Context.from_instance(inst, method=method, precision=precision)
+    ctx = pdr.Context.from_instance(inst, method=method, precision=precision, **opts)
     try:
         ctx.sweep(warmup)
         pdr.device_synchronize()
@@ -464,8 +464,12 @@ def main():
                                  ("eso_fp32", pdr.ESO, pdr.FP32_BULK),
                                  ("agd_fp32", pdr.AGD, pdr.FP32_BULK),
                                  ("gdm_fp32", pdr.GDM, pdr.FP32_BULK),
-                                 ("cap_fp64", pdr.CAP, pdr.FP64)):
-            r = time_variant(pdr, inst, meth, prec, args.steps, args.warmup)
+                                 ("cap_fp64", pdr.CAP, pdr.FP64),
+                                 # the LDS-tiled height kernel (pdr_options.height_kernel 2)
+                                 ("eso_fp64_tiled_height", pdr.ESO, pdr.FP64),
+                                 ("eso_fp32_tiled_height", pdr.ESO, pdr.FP32_BULK)):
+            opts = dict(height_kernel=2) if name.endswith("_tiled_height") else {}
+            r = time_variant(pdr, inst, meth, prec, args.steps, args.warmup, **opts)
             print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
             var[name] = dict(updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"],
                              kernel_ms_avg=r["kernel_ms_avg"], tiling=r["tiling"])

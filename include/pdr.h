@@ -112,6 +112,21 @@ typedef struct {
                               call or captured graph, not once per pass):
                               0 = automatic (4, at most B), else 1..4. Results
                               are the same bit for bit. */
+    int32_t height_kernel; /* excess -> height kernel of single instances:
+                              0 = automatic (the vertex-parallel kernel),
+                              1 = vertex-parallel, 2 = tiled: each block stages
+                              the rows of the arcs incident to up to 64 neighbouring
+                              vertices in LDS, 8 vectors at a time, so an arc
+                              with both ends in the tile is read from HBM once
+                              rather than once per end (pdr_init fails with
+                              PDR_ERR_INVALID when a vertex has more than 304
+                              incident arcs). The tiled kernel reads about a
+                              third less but runs slower on MI355X, its loads
+                              in flight being bounded by the LDS it stages
+                              through. Flows and heights are the same bit for
+                              bit; the objective's partial sums are grouped
+                              differently (last-bit differences). Batches use
+                              the vertex-parallel kernel. */
 } pdr_options;
 
 /* FP64 residual report of the current flows (see pdr_residual). */

@@ -64,7 +64,8 @@ class Options(C.Structure):
                 ("graph_sweeps", C.c_int32), ("height_chunk", C.c_int32),
                 ("cluster_size", C.c_int32), ("height_blocks", C.c_int32),
                 ("height_unroll", C.c_int32), ("z_log_capacity", C.c_int32),
-                ("cache_policy", C.c_int32), ("batch_groups", C.c_int32)]
+                ("cache_policy", C.c_int32), ("batch_groups", C.c_int32),
+                ("height_kernel", C.c_int32)]
 
 
 class Residual(C.Structure):
@@ -182,7 +183,7 @@ def _stream_handle(stream):
 def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, vec_per_lane=0,
                     z_feasible_tol=1e-8, agd=None, graph_sweeps=0, height_chunk=0,
                     cluster_size=0, height_blocks=0, height_unroll=0,
-                    cache_policy=0) -> Options:
+                    cache_policy=0, height_kernel=0) -> Options:
     opt = Options()
     lib().pdr_default_options(C.byref(opt))
     opt.method = int(method)
@@ -197,6 +198,7 @@ def default_options(method=ESO, precision=FP64, stream=None, lanes_per_arc=0, ve
     opt.height_blocks = int(height_blocks)
     opt.height_unroll = int(height_unroll)
     opt.cache_policy = int(cache_policy)
+    opt.height_kernel = int(height_kernel)
     if agd:  # overrides for the AGD or GDM parameters of the chosen method
         target = opt.gdm if int(method) == GDM else opt.agd
         for k, v in agd.items():
@@ -210,7 +212,7 @@ class Context:
     def __init__(self, n, row_ptr, col, u, s, t, d, method=ESO, precision=FP64, stream=None,
                  lanes_per_arc=0, vec_per_lane=0, z_feasible_tol=1e-8, agd=None, graph_sweeps=0,
                  height_chunk=0, cluster_size=0, height_blocks=0, height_unroll=0,
-                 cache_policy=0):
+                 cache_policy=0, height_kernel=0):
         L = lib()
         self._h = C.c_void_p()
         self._keep = [np.ascontiguousarray(row_ptr, np.int64), np.ascontiguousarray(col, np.int32),
@@ -220,7 +222,7 @@ class Context:
         self.n, self.m, self.K = int(n), int(cl.shape[0]), int(ss.shape[0])
         opt = default_options(method, precision, stream, lanes_per_arc, vec_per_lane,
                               z_feasible_tol, agd, graph_sweeps, height_chunk, cluster_size,
-                              height_blocks, height_unroll, cache_policy)
+                              height_blocks, height_unroll, cache_policy, height_kernel)
         st = L.pdr_init(C.byref(self._h), int(n), self.m, _ptr(rp), _ptr(cl), _ptr(uu), self.K,
                         _ptr(ss), _ptr(tt), _ptr(dd), C.byref(opt))
         if st != 0:

@@ -186,6 +186,7 @@ void set_height_chunk(pdr_ctx *c)
         grid = 2 * kHeightGridAuto;
     c->g.height_grid = c->req_height_grid > 0 ? c->req_height_grid : grid;
     c->g.height_unroll = c->req_height_unroll > 0 ? c->req_height_unroll : unroll;
+    c->g.tile_grid = c->req_height_grid > 0 ? c->req_height_grid : kTileGridAuto;
 }
 
 
@@ -248,15 +249,19 @@ pdr_status push_ctrl(pdr_ctx *c)
 // (height) and out-arcs (arc update) in this order, so the rows of f and h
 // that several vertices or arcs share are read close together in time. Only
 // the visiting order changes; the data layout and every result are the same.
+// cstart receives the first position of each cluster and then n (one
+// cluster, {0, n}, for the caller's order).
 void locality_order(int32_t n, const int32_t *rp, const int32_t *col,
                     const std::vector<int32_t> &in_ptr, const std::vector<int32_t> &in_idx,
                     const std::vector<int32_t> &tails, int32_t T, std::vector<int32_t> &vorder,
-                    std::vector<int32_t> &aorder)
+                    std::vector<int32_t> &aorder, std::vector<int32_t> &cstart)
 {
     vorder.clear();
     aorder.clear();
+    cstart.clear();
     if (T <= 1) {
         for (int32_t v = 0; v < n; ++v) vorder.push_back(v);
+        cstart.push_back(0);
     } else {
         std::vector<char> seen(n, 0), taken(n, 0);
         std::vector<int32_t> seeds, queue;
@@ -283,6 +288,7 @@ void locality_order(int32_t n, const int32_t *rp, const int32_t *col,
         int32_t cl = 0;
         for (int32_t sd : seeds) {
             if (taken[sd]) continue;
+            cstart.push_back((int32_t)vorder.size());
             queue.clear();
             queue.push_back(sd);
             stamp[sd] = cl;
@@ -306,8 +312,56 @@ void locality_order(int32_t n, const int32_t *rp, const int32_t *col,
             ++cl;
         }
     }
+    cstart.push_back(n);
     for (int32_t v : vorder)
         for (int32_t e = rp[v]; e < rp[v + 1]; ++e) aorder.push_back(e);
+}
+
+// Tiles of the tiled height kernel: runs of consecutive visiting positions
+// within one locality cluster, each closed before it would hold more than
+// kTileVerts vertices or kTileArcs distinct incident arcs. tinfo gets (first
+// position, end position, first slot, end slot) per tile, tarc the tile's
+// arcs in order of first incidence, tslot[p] the slot of vinc[p] in its
+// tile. Returns false when one vertex alone has more than kTileArcs incident
+// arcs (the vertex-parallel kernel then runs).
+bool build_tiles(int32_t m, const std::vector<int32_t> &vinfo, const std::vector<int32_t> &vinc,
+                 const std::vector<int32_t> &cstart, int32_t max_verts, int32_t max_arcs,
+                 std::vector<int32_t> &tinfo, std::vector<int32_t> &tarc,
+                 std::vector<uint16_t> &tslot)
+{
+    tinfo.clear();
+    tarc.clear();
+    tslot.assign(vinc.size(), 0);
+    std::vector<int32_t> mark((size_t)m, -1), slot_of((size_t)m, 0);
+    int32_t tiles = 0;
+    for (size_t ci = 0; ci + 1 < cstart.size(); ++ci) {
+        int32_t pos = cstart[ci];
+        const int32_t end = cstart[ci + 1];
+        while (pos < end) {
+            const int32_t first = pos, a0 = (int32_t)tarc.size();
+            int32_t na = 0;
+            while (pos < end && pos - first < max_verts) {
+                const int32_t p0 = vinfo[8 * (size_t)pos + 1], p1 = vinfo[8 * (size_t)pos + 3];
+                int32_t add = 0;
+                for (int32_t p = p0; p < p1; ++p) add += mark[vinc[p]] != tiles;
+                if (na + add > max_arcs) break;
+                for (int32_t p = p0; p < p1; ++p) {
+                    const int32_t e = vinc[p];
+                    if (mark[e] != tiles) {
+                        mark[e] = tiles;
+                        slot_of[e] = na++;
+                        tarc.push_back(e);
+                    }
+                    tslot[p] = (uint16_t)slot_of[e];
+                }
+                ++pos;
+            }
+            if (pos == first) return false;
+            tinfo.insert(tinfo.end(), {first, pos, a0, a0 + na});
+            ++tiles;
+        }
+    }
+    return true;
 }
 
 
@@ -411,6 +465,7 @@ void pdr_default_options(pdr_options *opt)
     opt->z_log_capacity = 0;
     opt->cache_policy = 0;
     opt->batch_groups = 0;
+    opt->height_kernel = 0;
 }
 
 const char *pdr_last_error(const pdr_ctx *ctx)
@@ -506,6 +561,8 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         return invalid("cache_policy must be 0, 1 or 2");
     if (opt.height_blocks < 0 || opt.height_blocks > pdr::kHeightBlocksMax)
         return invalid("height_blocks must be 0 or 1..8192");
+    if (opt.height_kernel < 0 || opt.height_kernel > 2)
+        return invalid("height_kernel must be 0, 1 or 2");
     if (opt.height_chunk < 0 || opt.height_chunk > 65536 ||
         (opt.height_chunk & (opt.height_chunk - 1)) != 0)
         return invalid("height_chunk must be 0 or a power of two up to 65536");
@@ -530,6 +587,7 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
     c->req_height_grid = opt.height_blocks;
     c->req_height_unroll = opt.height_unroll;
     c->req_cache_policy = opt.cache_policy;
+    c->req_height_kernel = opt.height_kernel;
     if (opt.z_log_capacity > 0) c->zlog_cap = opt.z_log_capacity;
     {
         pdr_status st = choose_tiling(c, c->precision, &c->tiling);
@@ -608,8 +666,9 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         }
     }
 
-    std::vector<int32_t> vorder, aorder;
-    locality_order(n, rp32.data(), col, in_ptr, in_idx, tails, c->cluster_size, vorder, aorder);
+    std::vector<int32_t> vorder, aorder, cstart;
+    locality_order(n, rp32.data(), col, in_ptr, in_idx, tails, c->cluster_size, vorder, aorder,
+                   cstart);
     {
         // the kernels index through these arrays: they must be permutations
         std::vector<char> hit_v(n, 0), hit_a(m > 0 ? m : 1, 0);
@@ -676,6 +735,22 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
         }
         PDR_UP(c->d_vinfo, vinfo.data(), 8 * (size_t)n);
         PDR_UP(c->d_vinc, vinc.data(), vinc.size());
+        if (c->req_height_kernel == 2) {
+            std::vector<int32_t> tinfo, tarc;
+            std::vector<uint16_t> tslot;
+            if (build_tiles(m, vinfo, vinc, cstart, pdr::kTileVerts, pdr::kTileArcs, tinfo, tarc,
+                            tslot)) {
+                c->ntiles = (int32_t)(tinfo.size() / 4);
+                if (tarc.empty()) tarc.push_back(0);
+                PDR_UP(c->d_tinfo, tinfo.data(), tinfo.size());
+                PDR_UP(c->d_tarc, tarc.data(), tarc.size());
+                PDR_UP(c->d_tslot, tslot.data(), tslot.size());
+            } else {
+                c->err = "height_kernel 2: a vertex has more incident arcs than a tile holds (" +
+                         std::to_string(pdr::kTileArcs) + ")";
+                return init_fail(c, PDR_ERR_INVALID, out);
+            }
+        }
     }
 #undef PDR_UP
     c->g = DevGraph{n,           m,         K,           c->Kp,        0,           0,         0,
@@ -683,6 +758,9 @@ static pdr_status pdr_init_body(pdr_ctx **out, int32_t n, int32_t m, const int64
                     c->d_deg,     c->d_inj_ptr, c->d_inj_k, c->d_inj_val, c->d_u,
                     c->d_s,       c->d_t,     c->d_d,       c->d_vorder, c->d_aorder,
                     c->d_vinfo,   c->d_vinc};
+    c->g.tinfo = c->d_tinfo;
+    c->g.tarc = c->d_tarc;
+    c->g.tslot = c->d_tslot;
     set_height_chunk(c);
     set_cache_policy(c);
 
@@ -1049,6 +1127,8 @@ void set_cache_policy(pdr_ctx *c)
     if (c->req_cache_policy == 1) temporal = true;
     if (c->req_cache_policy == 2) temporal = false;
     c->g.temporal = (temporal && !c->batch_member) ? 1 : 0;
+    // the tiled height kernel only on request: it reads less but runs slower
+    c->g.ntiles = c->req_height_kernel == 2 ? c->ntiles : 0;
 }
 
 pdr_status check_state_args(pdr_ctx *c, const double *f, const double *beta, const double *v,

@@ -28,6 +28,8 @@ constexpr int kHeightGridAuto = 2048;
 constexpr int kHeightUnrollAuto = 4;
 // Vertices per locality cluster of the visiting order.
 constexpr int kClusterAuto = 64;
+// Blocks of the tiled height kernel: four resident per CU (40 KiB of LDS each).
+constexpr int kTileGridAuto = 1024;
 // pdr_solve hands FP32 bulk over to the FP64 polish once z is within
 // kFloorFactor of the estimated FP32 floor z_noise / rate, the descent rate
 // measured over kRateWindows windows (kFloorFactorGdm for GDM, whose FP32
@@ -62,6 +64,8 @@ struct pdr_ctx {
     int32_t req_height_grid = 0;           // 0 = automatic
     int32_t req_height_unroll = 0;         // 0 = automatic
     int32_t req_cache_policy = 0;          // 0 = automatic, 1 = ordinary, 2 = non-temporal
+    int32_t req_height_kernel = 0;         // 0 = automatic, 1 = vertex-parallel, 2 = tiled
+    int32_t ntiles = 0;                    // tiles of the tiled height kernel (0: not used)
     hipStream_t cap_stream = nullptr;      // private stream used only for capture
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one per precision
     bool poisoned = false;
@@ -72,7 +76,8 @@ struct pdr_ctx {
     int32_t *d_row_ptr = nullptr, *d_tails = nullptr, *d_heads = nullptr, *d_in_ptr = nullptr,
             *d_in_idx = nullptr, *d_deg = nullptr, *d_inj_ptr = nullptr, *d_inj_k = nullptr,
             *d_s = nullptr, *d_t = nullptr, *d_vorder = nullptr, *d_aorder = nullptr,
-            *d_vinfo = nullptr, *d_vinc = nullptr;
+            *d_vinfo = nullptr, *d_vinc = nullptr, *d_tinfo = nullptr, *d_tarc = nullptr;
+    uint16_t *d_tslot = nullptr;
     double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
     // run state (device)
     double *f64 = nullptr, *h64 = nullptr, *v64 = nullptr;

@@ -21,6 +21,7 @@
 // No kernel uses atomics; every reduction order is fixed.
 #pragma once
 
+#include <limits.h>
 #include <math.h>
 
 #include "pdr_internal.h"
@@ -409,6 +410,223 @@ __global__ __launch_bounds__(256, (U <= 4 ? 8 : 1)) void k_height(DevGraph g, co
     if (!RESID && ctrl->stopped) return;
     height_core<T, RESID, U, NT>(g, f, h, h64, zpart, maxpart, Fsum,
                                  xcd_remap(blockIdx.x, gridDim.x), gridDim.x, blockIdx.x);
+}
+
+// ----------------------------------------------------------------- tiled excess -> height
+// The vertex-parallel kernel reads each flow row twice, once for each end of
+// its arc, and at benchmark sizes the second read mostly misses L2. Here a
+// block takes one unit (tile, run of R chunks of kTileVecs vectors) at a time
+// and, chunk by chunk, stages that chunk of every arc incident to the tile's
+// vertices in LDS, each arc once: an arc with both ends in the tile is read
+// from HBM once. Each (vertex, vector) item then sums its incident rows from
+// LDS in the order of the vertex-parallel kernel (in-arcs, then out-arcs, by
+// ascending id), so the excess and the heights are the same bits.
+// Everything that does not depend on the chunk is set up once per unit: the
+// row addresses each thread stages, its items' vertex records, the tile's
+// slot lists (in LDS) and a cursor into each item's sorted injection list
+// (moved forward as the chunks advance). The next chunk's loads are issued
+// before the current chunk's sums, so their latency overlaps the LDS work.
+// Units run run-major, so tiles sharing an arc stage the same chunks at
+// about the same time. LDS: about 39 KiB per block, four blocks per CU.
+constexpr int kTileThreads = 256;
+constexpr int kTileLoads = (kTileArcs * kTileVecs + kTileThreads - 1) / kTileThreads;
+constexpr int kTileItems = (kTileVerts * kTileVecs + kTileThreads - 1) / kTileThreads;
+static_assert(kTileThreads % kTileVecs == 0, "a thread keeps one vector slot of every chunk");
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kTileThreads, 4) void k_height_tiled(DevGraph g, int R, const T *__restrict__ f,
+                                                        T *__restrict__ h,
+                                                        double *__restrict__ zpart,
+                                                        const double *__restrict__ Fsum,
+                                                        const Ctrl *__restrict__ ctrl)
+{
+    if (ctrl->stopped) return;
+    constexpr int V = VecT<T>::N, CV = kTileVecs, TT = kTileThreads;
+    constexpr bool kNoise = sizeof(T) == 4;
+    __shared__ __attribute__((aligned(16))) T tile[kTileArcs * CV * V];
+    __shared__ uint16_t slots[2 * kTileArcs];
+    const int nvec = g.Kp / V;
+    const int64_t Kp = g.Kp;
+    const int nchunk = (nvec + CV - 1) / CV;
+    const int nrun = (nchunk + R - 1) / R;
+    const int64_t units = (int64_t)g.ntiles * nrun;
+    const int64_t nblk = gridDim.x;
+    const int tid = threadIdx.x;
+    const int v = tid % CV;  // the vector slot this thread stages and sums in every chunk
+    double zs = 0.0, ns = 0.0;
+    for (int64_t un = xcd_remap(blockIdx.x, nblk); un < units; un += nblk) {
+        const int r = (int)(un / g.ntiles);
+        const int t = (int)(un - (int64_t)r * g.ntiles);
+        const int4 ti = *reinterpret_cast<const int4 *>(g.tinfo + 4 * (int64_t)t);
+        const int nload = (ti.w - ti.z) * CV;
+        const int nitem = (ti.y - ti.x) * CV;
+        const int P0 = g.vinfo[8 * (int64_t)ti.x + 1];
+        const int P1 = g.vinfo[8 * (int64_t)(ti.y - 1) + 3];
+        const int c0 = r * R, c1 = min(c0 + R, nchunk);
+        for (int p = P0 + tid; p < P1; p += kTileThreads) slots[p - P0] = g.tslot[p];
+        int row[kTileLoads];  // arc staged by this thread in load j (-1: none)
+#pragma unroll
+        for (int j = 0; j < kTileLoads; ++j) {
+            const int idx = j * kTileThreads + tid;
+            row[j] = idx < nload ? g.tarc[ti.z + idx / CV] : -1;
+        }
+        int iv[kTileItems], ip0[kTileItems], ipin[kTileItems], ip1[kTileItems];
+        int cur[kTileItems], iend[kTileItems], nextk[kTileItems];
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) {
+            const int it = k * kTileThreads + tid;
+            iv[k] = -1;
+            ip0[k] = ipin[k] = ip1[k] = cur[k] = iend[k] = 0;
+            nextk[k] = INT_MAX;
+            if (it < nitem) {
+                const int pos = ti.x + it / CV;
+                const int4 vi = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos);
+                const int4 vj = *reinterpret_cast<const int4 *>(g.vinfo + 8 * (int64_t)pos + 4);
+                iv[k] = vi.x;
+                ip0[k] = vi.y - P0;
+                ipin[k] = vi.y + vi.z - P0;
+                ip1[k] = vi.w - P0;
+                // first injection at or after this item's first commodity
+                const int kstart = (c0 * CV + v) * V;
+                int lo = vj.x, hi = vj.y;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (g.inj_k[mid] < kstart) lo = mid + 1;
+                    else hi = mid;
+                }
+                cur[k] = lo;
+                iend[k] = vj.y;
+                nextk[k] = lo < vj.y ? g.inj_k[lo] : INT_MAX;
+            }
+        }
+        auto stage_loads = [&](int c, T (&x)[kTileLoads][V]) {
+            const int64_t off = (int64_t)(c * CV + v) * V;
+            const bool in = c * CV + v < nvec;
+#pragma unroll
+            for (int j = 0; j < kTileLoads; ++j) {
+                if (row[j] >= 0 && in) {
+                    load_vec(f + (int64_t)row[j] * Kp + off, x[j]);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < V; ++w) x[j][w] = (T)0;
+                }
+            }
+        };
+        auto put = [&](const T (&x)[kTileLoads][V]) {
+#pragma unroll
+            for (int j = 0; j < kTileLoads; ++j) {
+                const int idx = j * kTileThreads + tid;
+                if (idx < nload) store_vec(tile + idx * V, x[j]);
+            }
+        };
+        auto sum_chunk = [&](int c) {
+            const int q = c * CV + v;
+            if (q >= nvec) return;
+            const int k0 = q * V;
+#pragma unroll
+            for (int k = 0; k < kTileItems; ++k) {
+                if (iv[k] < 0) continue;
+                double acc[V];
+                float mag[V];
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    acc[w] = 0.0;
+                    mag[w] = 0.0f;
+                }
+                // four incident rows read from LDS before they are summed (in
+                // order, so the grouping does not change the bits)
+                for (int p = ip0[k]; p < ip1[k]; p += 4) {
+                    int sl[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) sl[b] = slots[p + b < ip1[k] ? p + b : p];
+                    T xv[4][V];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) load_vec(tile + (sl[b] * CV + v) * V, xv[b]);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (p + b < ip1[k]) {
+                            const double sg = p + b < ipin[k] ? 1.0 : -1.0;
+#pragma unroll
+                            for (int w = 0; w < V; ++w) {
+                                acc[w] += sg * (double)xv[b][w];
+                                if constexpr (kNoise) mag[w] += fabsf((float)xv[b][w]);
+                            }
+                        }
+                }
+                // injections in [k0, k0 + V); those below k0 belong to other
+                // vector slots and are passed over
+                while (nextk[k] < k0 + V) {
+                    if (nextk[k] >= k0) {
+                        const int kk = nextk[k] - k0;
+                        const double val = g.inj_val[cur[k]];
+#pragma unroll
+                        for (int w = 0; w < V; ++w)
+                            if (w == kk) {
+                                acc[w] += val;
+                                if constexpr (kNoise) mag[w] += (float)fabs(val);
+                            }
+                    }
+                    ++cur[k];
+                    nextk[k] = cur[k] < iend[k] ? g.inj_k[cur[k]] : INT_MAX;
+                }
+                const int dg = ip1[k] - ip0[k];
+                T hv[V];
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double hh = dg > 0 ? acc[w] / (double)dg : 0.0;
+                    hv[w] = (T)hh;
+                    zs += acc[w] * hh;
+                    if constexpr (kNoise) {
+                        const double rr = kFp32Unit * (double)mag[w];
+                        if (dg > 0) ns += rr * rr / (double)dg;
+                    }
+                }
+                store_vec_s<NT>(h + (int64_t)iv[k] * Kp + k0, hv);
+            }
+        };
+        // chunk c + 1 is loaded into registers while chunk c is summed
+        T xa[kTileLoads][V];
+        stage_loads(c0, xa);
+        for (int c = c0; c < c1; ++c) {
+            __syncthreads();  // the previous chunk's sums are done with the tile
+            put(xa);
+            if (c + 1 < c1) stage_loads(c + 1, xa);
+            __syncthreads();
+            sum_chunk(c);
+        }
+        __syncthreads();  // the next unit rewrites the slot lists and the tile
+    }
+    double ps = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kTileThreads + tid; e < g.m; e += nblk * kTileThreads) {
+        const double over = Fsum[e] - g.u[e];
+        if (over > 0.0) ps += over * over;
+    }
+    zs = wave_sum(zs);
+    ps = wave_sum(ps);
+    if constexpr (kNoise) ns = wave_sum(ns);
+    // the staging area is free here (every unit ended with a barrier)
+    constexpr int NW = TT / 64;
+    double *sh = reinterpret_cast<double *>(tile);
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
+        sh[w] = zs;
+        sh[NW + w] = ps;
+        sh[2 * NW + w] = ns;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = sh[0], b = sh[NW], cc = sh[2 * NW];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            a += sh[q];
+            b += sh[NW + q];
+            cc += sh[2 * NW + q];
+        }
+        const int64_t part = blockIdx.x;
+        zpart[part] = a;
+        zpart[nblk + part] = b;
+        zpart[2 * nblk + part] = cc;
+    }
 }
 
 // Batched: hmap[logical block] = (instance, block within the instance); the

@@ -60,7 +60,22 @@ struct DevGraph {
     // the sweep kernels use ordinary loads and stores and the data stays
     // resident between passes; 0: they stream with non-temporal hints.
     int32_t temporal;
+    // Tiles of the tiled height kernel (ntiles 0: the vertex-parallel kernel
+    // runs instead). Tile t covers visiting positions [tinfo[4t], tinfo[4t+1])
+    // and the arcs tarc[tinfo[4t+2] .. tinfo[4t+3]) incident to them (each
+    // once); tslot[p] is the index of arc vinc[p] in its vertex's tile list.
+    int32_t ntiles;
+    int32_t tile_grid;       // blocks of the tiled height kernel
+    const int32_t *tinfo;    // 4 * ntiles, 16-byte aligned
+    const int32_t *tarc;
+    const uint16_t *tslot;   // 2m, parallel to vinc
 };
+
+// Tiled height kernel: at most kTileVerts vertices and kTileArcs incident arcs
+// per tile; a block stages kTileVecs 16-byte vectors of each arc in LDS.
+constexpr int kTileVerts = 64;
+constexpr int kTileArcs = 304;
+constexpr int kTileVecs = 8;
 
 struct AgdParams {
     double beta_min, beta_max, alpha_inc, alpha_dec;

@@ -145,10 +145,44 @@ static void height_launch(const DevGraph &g, const T *f, T *h, double *zpart, co
                                                         ctrl);
 }
 
+// Chunks per unit of the tiled height kernel: about four units per block, so
+// the per-unit set-up is spread over many chunks and the last units even out.
+static int tile_run(const DevGraph &g, int V, unsigned nb)
+{
+    const int64_t nchunk = ((int64_t)(g.Kp / V) + kTileVecs - 1) / kTileVecs;
+    const int64_t per = 4 * (int64_t)nb;
+    int64_t R = ((int64_t)g.ntiles * nchunk + per - 1) / per;
+    if (R < 1) R = 1;
+    return (int)(R < nchunk ? R : nchunk);
+}
+
+template <typename T>
+static void height_tiled_launch(const DevGraph &g, const T *f, T *h, double *zpart,
+                                const double *Fsum, Ctrl *ctrl, unsigned nb, hipStream_t st)
+{
+    const int R = tile_run(g, VecT<T>::N, nb);
+    if (g.temporal)
+        k_height_tiled<T, false><<<nb, kTileThreads, 0, st>>>(g, R, f, h, zpart, Fsum, ctrl);
+    else
+        k_height_tiled<T, true><<<nb, kTileThreads, 0, st>>>(g, R, f, h, zpart, Fsum, ctrl);
+}
+
 hipError_t launch_height(const DevGraph &g, bool fp64, const void *f, void *h, double *zpart,
                          const double *Fsum, Ctrl *ctrl, double *zlog, int64_t zmask,
                          hipStream_t st)
 {
+    if (g.ntiles > 0) {
+        const unsigned nb = (unsigned)g.tile_grid;
+        if (fp64)
+            height_tiled_launch<double>(g, (const double *)f, (double *)h, zpart, Fsum, ctrl, nb,
+                                        st);
+        else
+            height_tiled_launch<float>(g, (const float *)f, (float *)h, zpart, Fsum, ctrl, nb, st);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_reduce<<<1, 1024, 0, st>>>(zpart, (int)nb, ctrl, zlog, zmask);
+        return hipGetLastError();
+    }
     const unsigned nb = (unsigned)height_blocks(g, fp64 ? 8 : 4);
     bool launched = false;
 #define PDR_H(U_)                                                                               \

@@ -181,6 +181,70 @@ def test_cache_hints_do_not_change_the_iterates(method, precision):
         assert np.max(np.abs(runs[0][0] - st.f)) <= flow_tol(inst)
 
 
+def _hub_instance(spokes, K, seed):
+    """Vertex 0 joined both ways to vertices 1..spokes, plus a two-way ring
+    through 1..spokes + 9: vertex 0 has 2 * spokes incident arcs."""
+    n = spokes + 10
+    arcs = set()
+    for v in range(1, spokes + 1):
+        arcs |= {(0, v), (v, 0)}
+    for v in range(1, n):
+        w = v + 1 if v + 1 < n else 1
+        arcs |= {(v, w), (w, v)}
+    rng = np.random.default_rng(seed)
+    s = rng.integers(0, n, size=K)
+    t = (s + rng.integers(1, n, size=K)) % n
+    d = rng.integers(1, 6, size=K).astype(np.float64)
+    return make_instance(n, sorted(arcs), rng.integers(3, 40, size=len(arcs)), s, t, d)
+
+
+TILED_CASES = [
+    # several tiles per locality cluster, ragged last chunk (Kp / V not a multiple of 8)
+    ("knn300_k333", lambda: recipe_small("knn", 300, 333, seed=12, u_range=(2, 30), d_range=(1, 6))),
+    ("grid12_k61", lambda: recipe_small("grid", 12, 61, seed=13, u_range=(2, 20), d_range=(1, 6))),
+    # a vertex with 280 incident arcs: its tile closes on the 304-arc cap
+    ("hub140_k77", lambda: _hub_instance(140, 77, seed=14)),
+]
+
+
+@pytest.mark.parametrize("precision", [pdr.FP64, pdr.FP32_BULK])
+@pytest.mark.parametrize("method", ALL)
+@pytest.mark.parametrize("case", [c[0] for c in TILED_CASES])
+def test_tiled_height_kernel_matches_vertex_parallel(case, method, precision):
+    """The LDS-tiled height kernel (height_kernel 2) sums each excess in the
+    vertex-parallel kernel's order: flows, heights and learning rates agree bit
+    for bit over 30 passes; the objective only in its partial sums' grouping."""
+    inst = dict(TILED_CASES)[case]()
+    gm, om = METHODS[method]
+    T = 30
+    runs = []
+    for hk in (1, 2):
+        with ctx_for(inst, gm, precision, height_kernel=hk) as c:
+            c.sweep(T)
+            runs.append((c.flows(), c.heights(), c.learning_rates(), c.z_log(0, T)))
+    say("tiled height", case, method, precision, "z", runs[0][3][-1], runs[1][3][-1])
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+    np.testing.assert_allclose(runs[1][3], runs[0][3], rtol=1e-12, atol=0)
+    if precision == pdr.FP64:
+        st, _ = oracle.run(inst, om, T)
+        assert np.max(np.abs(runs[1][0] - st.f)) <= flow_tol(inst)
+
+
+def test_tiled_height_kernel_refuses_a_vertex_beyond_one_tile():
+    """A vertex with more incident arcs than a tile holds (304) cannot take the
+    tiled kernel: pdr_init answers PDR_ERR_INVALID; the default kernel runs."""
+    inst = _hub_instance(160, 20, seed=15)
+    with pytest.raises(pdr.PdrError) as ei:
+        ctx_for(inst, pdr.ESO, height_kernel=2)
+    assert ei.value.status == 1 and "304" in str(ei.value)
+    with ctx_for(inst, pdr.ESO) as c:
+        c.sweep(5)
+        st, _ = oracle.run(inst, oracle.ESO, 5)
+        assert np.max(np.abs(c.flows() - st.f)) <= flow_tol(inst)
+
+
 @pytest.mark.parametrize("K", [1, 2, 3, 5, 31, 33, 63, 65, 127, 129, 255, 257, 1000, 1025, 3001])
 @pytest.mark.parametrize("method", ALL)
 def test_ragged_commodity_counts(method, K):
