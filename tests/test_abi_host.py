@@ -125,6 +125,10 @@ def test_init_rejects_isolated_commodity_endpoint():
     (dict(lanes_per_arc=1, vec_per_lane=1), "tiling"),  # K=100 needs more than 1 x 1 vectors
     (dict(cache_policy=3), "cache_policy"),
     (dict(cache_policy=-1), "cache_policy"),
+    (dict(height_kernel=3), "height_kernel"),
+    (dict(height_kernel=-1), "height_kernel"),
+    (dict(height_chunk=48), "height_chunk"),
+    (dict(height_chunk=131072), "height_chunk"),
 ])
 def test_init_rejects_invalid_options(opts, fragment):
     a = _good()
