@@ -201,8 +201,8 @@ pdr_status pdr_sweep(pdr_ctx *ctx, int64_t max_sweeps, double eps_obj, double z_
  * on the windows' smallest z over the last four windows). When the window's
  * smallest z is <= floor_factor * z_noise / rate (floor_factor <= 0 means 5,
  * or 0.03 for PDR_GDM, whose FP32 descent goes on far below the estimate),
- * or when z stalls (four windows in a row whose smallest z is not below
- * (1 - 1e-3) times the smallest before), the flows are widened to FP64
+ * or when z stalls (four windows in a row whose smallest z is not below the
+ * smallest before by more than 10 z_noise), the flows are widened to FP64
  * exactly (as pdr_set_precision) and the run finishes in FP64: the FP64 polish.
  * The rate and stall tracking carries over from one call to the next, so a
  * long run may be split into calls; pdr_set_state, pdr_set_state_noalloc and

@@ -897,9 +897,12 @@ static pdr_status pdr_solve_body(pdr_ctx *c, double z_target, int64_t max_sweeps
             }
             const bool near_floor = rate > 0.0 && cur <= kappa * (c->h_ctrl->z_noise / rate);
             // a stall is kStallWindows windows in a row without a new lowest z
-            // (GDM's objective is not monotone: one window can miss the last
-            // trough and still be on the way down)
-            stalled = cur < (1.0 - 1e-3) * best_before ? 0 : stalled + 1;
+            // by more than the FP32 noise could account for (GDM's objective is
+            // not monotone: one window can miss the last trough and still be on
+            // the way down; a slow but steady descent, as AGD's at 10^4
+            // commodities, gains far more than the noise per window)
+            const double margin = std::max(kStallNoise * c->h_ctrl->z_noise, 1e-12 * best_before);
+            stalled = cur < best_before - margin ? 0 : stalled + 1;
             const double best_now = std::min(best_before, cur);
             if (near_floor || stalled >= kStallWindows) {
                 st = pdr_set_precision(c, PDR_FP64);  // also resets the tracking

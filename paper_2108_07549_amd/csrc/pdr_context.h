@@ -40,6 +40,9 @@ constexpr double kFloorFactor = 5.0;
 constexpr double kFloorFactorGdm = 0.03;
 constexpr int kRateWindows = 4;
 constexpr int kStallWindows = 4;
+// a window that lowers the lowest z by at most this many z_noise counts as
+// no progress
+constexpr double kStallNoise = 10.0;
 // Flows + heights (+ velocities) of one pass at or below this size are kept
 // cache-resident (the MI355X Infinity Cache holds 256 MB).
 constexpr double kCacheResidentBytes = 256.0 * 1024.0 * 1024.0;
