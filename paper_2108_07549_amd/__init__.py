@@ -391,7 +391,7 @@ class Batch:
 
     def __init__(self, instances, method=ESO, precision=FP64, stream=None, agd=None,
                  graph_sweeps=0, z_log_capacity=0, lanes_per_arc=0, vec_per_lane=0,
-                 height_blocks=0, groups=0):
+                 height_blocks=0, groups=0, height_chunk=0):
         L = lib()
         self._h = C.c_void_p()
         keep, arr = [], (Instance * len(instances))()
@@ -408,6 +408,7 @@ class Batch:
         opt.z_log_capacity = int(z_log_capacity)
         opt.height_blocks = int(height_blocks)
         opt.batch_groups = int(groups)
+        opt.height_chunk = int(height_chunk)
         st = L.pdr_batch_init(C.byref(self._h), len(instances), arr, C.byref(opt))
         if st != 0:
             raise PdrError(st, L.pdr_batch_last_error(None).decode())
