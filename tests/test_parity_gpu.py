@@ -232,6 +232,22 @@ def test_tiled_height_kernel_matches_vertex_parallel(case, method, precision):
         assert np.max(np.abs(runs[1][0] - st.f)) <= flow_tol(inst)
 
 
+def test_tiled_height_kernel_with_streamed_rows():
+    """The tiled height kernel with rows that take the streamed arc kernels
+    (K = 16,385): flows and heights equal the vertex-parallel kernel's bit for
+    bit after 6 passes of ESO and of AGD."""
+    inst = recipe_small("knn", 210, 16385, seed=78, u_range=(20, 1600), d_range=(1, 5))
+    for gm in (pdr.ESO, pdr.AGD):
+        runs = []
+        for hk in (1, 2):
+            with ctx_for(inst, gm, pdr.FP64, height_kernel=hk) as c:
+                assert c.tiling()[1] < 0
+                c.sweep(6)
+                runs.append((c.flows(), c.heights()))
+        assert np.array_equal(runs[0][0], runs[1][0])
+        assert np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_tiled_height_kernel_refuses_a_vertex_beyond_one_tile():
     """A vertex with more incident arcs than a tile holds (304) cannot take the
     tiled kernel: pdr_init answers PDR_ERR_INVALID; the default kernel runs."""
