@@ -901,8 +901,11 @@ static pdr_status pdr_solve_body(pdr_ctx *c, double z_target, int64_t max_sweeps
             // not monotone: one window can miss the last trough and still be on
             // the way down; a slow but steady descent, as AGD's at 10^4
             // commodities, gains far more than the noise per window)
-            const double margin = std::max(kStallNoise * c->h_ctrl->z_noise, 1e-12 * best_before);
-            stalled = cur < best_before - margin ? 0 : stalled + 1;
+            // (the first window after a start or a reset has nothing to beat)
+            const bool progress =
+                !std::isfinite(best_before) ||
+                cur < best_before - std::max(kStallNoise * c->h_ctrl->z_noise, 1e-12 * best_before);
+            stalled = progress ? 0 : stalled + 1;
             const double best_now = std::min(best_before, cur);
             if (near_floor || stalled >= kStallWindows) {
                 st = pdr_set_precision(c, PDR_FP64);  // also resets the tracking
