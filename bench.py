@@ -245,15 +245,25 @@ def batch_verdicts(pdr, insts, method, seconds, members=96, chunk=5000):
     with pdr.Batch(insts, method=method, precision=pdr.FP64) as b:
         t0 = time.perf_counter()
         passes = 0
+        timeline = []  # (passes, seconds, members decided) about once a minute
+        next_mark = 60.0
         while True:
             b.sweep(chunk)
             pdr.device_synchronize()
             passes += chunk
-            if time.perf_counter() - t0 >= seconds:
+            el = time.perf_counter() - t0
+            print(f"[bench] batch verdicts: {passes} passes, {el:.0f} s", file=sys.stderr,
+                  flush=True)
+            if el >= next_mark or el >= seconds:
+                dec = sum(b.member(q).residual()["verdict"] != "undecided"
+                          for q in range(len(insts)))
+                timeline.append(dict(passes=passes, seconds=el, decided=int(dec)))
+                next_mark += 60.0
+            if el >= seconds:
                 break
         sec = time.perf_counter() - t0
         out = dict(members=len(insts), passes=passes, seconds=sec, decided=0, agree=0,
-                   disagree=0, undecided=0, by_label={})
+                   disagree=0, undecided=0, by_label={}, timeline=timeline)
         for q, inst in enumerate(insts):
             v = b.member(q).residual()["verdict"]
             lab = inst.meta.get("certified", "uncertified")
