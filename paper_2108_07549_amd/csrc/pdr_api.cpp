@@ -225,6 +225,17 @@ pdr_status ensure_buffers(pdr_ctx *c, int32_t precision)
         if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (h)");
         PDR_CHECK(c, e);
     }
+    // undo rows of the streamed AGD / GDM kernels, sized for FP64 rows so they
+    // serve either precision; needed when FP64 rows are streamed (or a
+    // streamed tiling was asked for)
+    const bool agd_like = c->method == PDR_AGD || c->method == PDR_GDM;
+    if (agd_like && !c->d_undo && (c->Kp / 2 > pdr::max_tiling_vectors() || c->req_nv < 0)) {
+        const size_t rows = (size_t)pdr::kStreamSlots * (c->method == PDR_GDM ? 2 : 1);
+        hipError_t e = dalloc(c, &c->d_undo, rows * (size_t)c->Kp);
+        if (e == hipErrorOutOfMemory) return fail(c, PDR_ERR_OOM, "out of device memory (undo rows)");
+        PDR_CHECK(c, e);
+    }
+    c->g.stream_undo = c->d_undo;
     return PDR_OK;
 }
 

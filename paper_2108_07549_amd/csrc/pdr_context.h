@@ -84,6 +84,7 @@ struct pdr_ctx {
     double *d_inj_val = nullptr, *d_u = nullptr, *d_d = nullptr;
     // run state (device)
     double *f64 = nullptr, *h64 = nullptr, *v64 = nullptr;
+    double *d_undo = nullptr;              // undo rows of the streamed AGD / GDM kernels
     float *f32 = nullptr, *h32 = nullptr, *v32 = nullptr;
     double *Fsum = nullptr, *beta = nullptr, *zpart = nullptr, *maxpart = nullptr,
            *arcpart = nullptr, *resout = nullptr, *zlog = nullptr;

@@ -1204,18 +1204,22 @@ __global__ __launch_bounds__(kStreamLanes) void k_eso_stream(DevGraph g, T *__re
                                lds);
 }
 
-// AGD (vel == nullptr) or GDM arc step on a streamed row: the first pass sums
-// df, df (df - g) and the new row's values; an accepted step recomputes and
-// stores the row in a second pass.
+// AGD (vel == nullptr) or GDM arc step on a streamed row, in one pass over
+// it: each vector's stepped values (new flows, and velocities) are stored in
+// place at once, its old values in the block's undo rows (uf, uv), while the
+// sums of df, df (df - g) and the new values are formed; a rejected step then
+// copies the old values back. An accepted step (the common case: the rate
+// falls on a rejection and grows only every inc_period passes) so reads the
+// row, h_i and h_j once instead of twice.
 template <typename T, int TV, bool GDM>
 __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict__ f,
                                                T *__restrict__ vel, const T *__restrict__ h,
                                                double *__restrict__ Fsum, double *__restrict__ beta,
                                                const AgdParams &prm, const Ctrl *__restrict__ ctrl,
-                                               int64_t slot, int lane, double *lds)
+                                               int64_t slot, int lane, double *lds, int &phase,
+                                               T *__restrict__ uf, T *__restrict__ uv)
 {
     constexpr int L = kStreamLanes, V = VecT<T>::N;
-    int phase = 0;
     const int64_t e = g.aorder[slot];
     const int64_t Kp = g.Kp;
     const int nvec = g.Kp / V;
@@ -1228,40 +1232,41 @@ __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict_
     const double psi = F > u ? F - u : 0.0;
     const double b = beta[e];
     const double gam = prm.gamma;
-    // the stepped values of vector q: new flows (and velocities)
-    auto step = [&](int q, T (&nf)[V], T (&nv)[V], double (&r)[3]) {
-        T a[V], bb[V], x[V], w0[V];
-        load_vec(fe + q * V, x);
-        if constexpr (GDM) load_vec(ve + q * V, w0);
-        load_vec(hi + q * V, a);
-        load_vec(hj + q * V, bb);
-#pragma unroll
-        for (int w = 0; w < V; ++w) {
-            const double gg = (double)(a[w] - bb[w]);
-            const double fx = (double)x[w];
-            const double st = b * (gg - psi);
-            const double df = st > -fx ? st : -fx;
-            if constexpr (GDM) {
-                const double vn = gam * (double)w0[w] + df;
-                const double fn = fx + vn;
-                nv[w] = (T)vn;
-                nf[w] = (T)(fn > 0.0 ? fn : 0.0);
-            } else {
-                nf[w] = (T)(fx + df);
-            }
-            r[0] += df;
-            r[1] += df * (df - gg);
-            r[2] += (double)nf[w];
-        }
-    };
-    double red[3] = {0.0, 0.0, 0.0};
+    double red[3] = {0.0, 0.0, 0.0};  // sum df, sum df (df - g), sum of the new values
     for (int base = 0; base < nvec; base += L * TV)
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T nf[V], nv[V];
-                step(q, nf, nv, red);
+                T a[V], bb[V], x[V], w0[V], nf[V], nv[V];
+                load_vec(fe + q * V, x);
+                if constexpr (GDM) load_vec(ve + q * V, w0);
+                load_vec(hi + q * V, a);
+                load_vec(hj + q * V, bb);
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    const double gg = (double)(a[w] - bb[w]);
+                    const double fx = (double)x[w];
+                    const double st = b * (gg - psi);
+                    const double df = st > -fx ? st : -fx;
+                    if constexpr (GDM) {
+                        const double vn = gam * (double)w0[w] + df;
+                        const double fn = fx + vn;
+                        nv[w] = (T)vn;
+                        nf[w] = (T)(fn > 0.0 ? fn : 0.0);
+                    } else {
+                        nf[w] = (T)(fx + df);
+                    }
+                    red[0] += df;
+                    red[1] += df * (df - gg);
+                    red[2] += (double)nf[w];
+                }
+                store_vec_s<true>(uf + q * V, x);
+                store_vec_s<true>(fe + q * V, nf);
+                if constexpr (GDM) {
+                    store_vec_s<true>(uv + q * V, w0);
+                    store_vec_s<true>(ve + q * V, nv);
+                }
             }
         }
     group_sum<L, 3>(red, lds, phase);
@@ -1271,17 +1276,21 @@ __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict_
                              : 0.5 * ((after > 0.0 ? after * after : 0.0) -
                                       (before > 0.0 ? before * before : 0.0));
     const bool accept = dcong + red[1] <= 0.0;
-    if (accept) {
+    if (!accept) {
+        // each lane restores the vectors it wrote itself
         for (int base = 0; base < nvec; base += L * TV)
 #pragma unroll
             for (int v = 0; v < TV; ++v) {
                 const int q = base + v * L + lane;
                 if (q < nvec) {
-                    T nf[V], nv[V];
-                    double dummy[3] = {0.0, 0.0, 0.0};
-                    step(q, nf, nv, dummy);
-                    store_vec_s<true>(fe + q * V, nf);
-                    if constexpr (GDM) store_vec_s<true>(ve + q * V, nv);
+                    T x[V];
+                    load_vec(uf + q * V, x);
+                    store_vec_s<true>(fe + q * V, x);
+                    if constexpr (GDM) {
+                        T w0[V];
+                        load_vec(uv + q * V, w0);
+                        store_vec_s<true>(ve + q * V, w0);
+                    }
                 }
             }
     }
@@ -1295,6 +1304,9 @@ __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict_
     }
 }
 
+// The streamed AGD / GDM kernels run kStreamSlots blocks (one per CU, as their
+// registers allow) in a grid-stride loop over the arcs, each block with its
+// own undo rows.
 template <typename T, int TV, bool GDM>
 __global__ __launch_bounds__(kStreamLanes) void k_agd_stream(DevGraph g, T *__restrict__ f,
                                                              T *__restrict__ vel,
@@ -1302,12 +1314,22 @@ __global__ __launch_bounds__(kStreamLanes) void k_agd_stream(DevGraph g, T *__re
                                                              double *__restrict__ Fsum,
                                                              double *__restrict__ beta,
                                                              AgdParams prm,
-                                                             const Ctrl *__restrict__ ctrl)
+                                                             const Ctrl *__restrict__ ctrl,
+                                                             T *__restrict__ undo)
 {
     if (ctrl->stopped) return;
     __shared__ double lds[2 * kRedMax * (kStreamLanes / 64)];
-    agd_arc_stream<T, TV, GDM>(g, f, vel, h, Fsum, beta, prm, ctrl,
-                               xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x, lds);
+    const int64_t Kp = g.Kp;
+    T *uf = undo + (int64_t)blockIdx.x * (GDM ? 2 : 1) * Kp;
+    T *uv = GDM ? uf + Kp : nullptr;
+    const int64_t nblk = gridDim.x;
+    // the reduction buffer's halves alternate across the block's arcs too, so
+    // a wave that runs ahead into the next arc's reduction cannot overwrite
+    // values a slower wave is still reading
+    int phase = 0;
+    for (int64_t s = xcd_remap(blockIdx.x, nblk); s < g.m; s += nblk)
+        agd_arc_stream<T, TV, GDM>(g, f, vel, h, Fsum, beta, prm, ctrl, s, (int)threadIdx.x, lds,
+                                   phase, uf, uv);
 }
 
 // Fsum of a streamed row.

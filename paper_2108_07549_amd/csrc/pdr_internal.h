@@ -64,6 +64,10 @@ struct DevGraph {
     // runs instead). Tile t covers visiting positions [tinfo[4t], tinfo[4t+1])
     // and the arcs tarc[tinfo[4t+2] .. tinfo[4t+3]) incident to them (each
     // once); tslot[p] is the index of arc vinc[p] in its vertex's tile list.
+    // Undo rows of the streamed AGD / GDM kernels: (GDM ? 2 : 1) rows of Kp
+    // FP64-sized elements for each of their kStreamSlots blocks (null unless
+    // the context's rows are streamed and the method is AGD or GDM).
+    void *stream_undo;
     int32_t ntiles;
     int32_t tile_grid;       // blocks of the tiled height kernel
     const int32_t *tinfo;    // 4 * ntiles, 16-byte aligned
@@ -94,6 +98,8 @@ struct Tiling {
 };
 // The one streamed tiling.
 Tiling streamed_tiling();
+// Blocks of the streamed AGD / GDM kernels, each with its own undo rows.
+constexpr int kStreamSlots = 256;
 
 // One instance of a batch as the batched kernels see it (device-resident
 // array, one entry per instance). All instances of a batch share one storage

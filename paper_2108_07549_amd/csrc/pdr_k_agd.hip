@@ -27,16 +27,25 @@ hipError_t launch_agd(const DevGraph &g, bool fp64, Tiling tl, void *f, const vo
 {
     if (g.m == 0) return hipSuccess;
     if (tl.lanes == kStreamLanes && tl.nv == -kStreamTile) {  // streamed long rows
-        const unsigned nb = (unsigned)g.m;
+        if (!g.stream_undo) return hipErrorInvalidValue;
+        const unsigned nb = (unsigned)(g.m < kStreamSlots ? g.m : kStreamSlots);
         constexpr int TV = kStreamTile;
         if (fp64 && vel)
-            k_agd_stream<double, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, (double *)vel, (const double *)h, Fsum, beta, prm, ctrl);
+            k_agd_stream<double, TV, true><<<nb, kStreamLanes, 0, st>>>(
+                g, (double *)f, (double *)vel, (const double *)h, Fsum, beta, prm, ctrl,
+                (double *)g.stream_undo);
         else if (fp64)
-            k_agd_stream<double, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (double *)f, nullptr, (const double *)h, Fsum, beta, prm, ctrl);
+            k_agd_stream<double, TV, false><<<nb, kStreamLanes, 0, st>>>(
+                g, (double *)f, nullptr, (const double *)h, Fsum, beta, prm, ctrl,
+                (double *)g.stream_undo);
         else if (vel)
-            k_agd_stream<float, TV, true><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, (float *)vel, (const float *)h, Fsum, beta, prm, ctrl);
+            k_agd_stream<float, TV, true><<<nb, kStreamLanes, 0, st>>>(
+                g, (float *)f, (float *)vel, (const float *)h, Fsum, beta, prm, ctrl,
+                (float *)g.stream_undo);
         else
-            k_agd_stream<float, TV, false><<<nb, kStreamLanes, 0, st>>>(g, (float *)f, nullptr, (const float *)h, Fsum, beta, prm, ctrl);
+            k_agd_stream<float, TV, false><<<nb, kStreamLanes, 0, st>>>(
+                g, (float *)f, nullptr, (const float *)h, Fsum, beta, prm, ctrl,
+                (float *)g.stream_undo);
         return hipGetLastError();
     }
 #define PDR_AGD_CASE(L_, NV_)                                                                  \
