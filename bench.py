@@ -193,8 +193,10 @@ def time_to_target(pdr, inst, method, precision, target, cap, window=512, chunk=
 
 def time_batch(pdr, B, seed, method, precision, steps, warmup, tune_reps):
     """Batched sweeps of the uneven B-instance recipe: wall-clock updates/s of
-    plain sweeps (graph replays) before and after the tiling autotuner, and the
-    per-launch split from HIP events."""
+    plain sweeps before and after the tiling autotuner, and the per-launch
+    split from HIP events. With steps and warmup multiples of the batch's
+    graph length (32 passes) the timed passes are graph replays, the warm-up
+    capturing the graphs."""
     from gen.batch import recipe_batch
     t0 = time.perf_counter()
     insts = recipe_batch(B, seed)
@@ -519,7 +521,7 @@ def main():
     if not args.no_batch:
         bat = {}
         for name, prec in (("eso_fp32", pdr.FP32_BULK), ("eso_fp64", pdr.FP64)):
-            r = time_batch(pdr, 256, 4, pdr.ESO, prec, 10, 3, 3)
+            r = time_batch(pdr, 256, 4, pdr.ESO, prec, 64, 32, 3)
             print(f"[bench] batch {name}: auto {r['auto']['ms_per_step']:.3f} ms/sweep, tuned "
                   f"{r['tuned']['ms_per_step']:.3f} ms/sweep", file=sys.stderr, flush=True)
             bat[name] = r

@@ -62,14 +62,18 @@ struct pdr_batch {
     int32_t req_groups = 0;       // 0: automatic (kBranches, at most B)
     int32_t *d_count = nullptr;
     int32_t *h_count = nullptr;
-    // arc launches of different buckets run on these streams side by side,
-    // forked from and joined back to the pass's stream with events
+    // group g's launches run on aux[g] (group 0 on the batch's stream),
+    // forked from and joined back to the batch's stream with events
     static constexpr int kBranches = 4;
     hipStream_t aux[kBranches] = {};
     hipEvent_t fork = nullptr, join[kBranches] = {};
-    hipStream_t cap_aux[kBranches] = {};
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // One captured graph of graph_sweeps passes per group, each launched on
+    // its group's stream: the runtime replays a graph's nodes on the stream it
+    // is launched on, one after another, so branches inside one graph would
+    // not overlap.
+    hipGraphExec_t gexec[kBranches] = {};
+    bool have_graphs = false;
     bool poisoned = false;
     std::string err;
 };
@@ -138,8 +142,11 @@ hipError_t upload_vec(T **p, const std::vector<T> &v, hipStream_t st)
 
 void drop_graph(pdr_batch *b)
 {
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
+    for (auto &ge : b->gexec) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+    }
+    b->have_graphs = false;
 }
 
 // Block map of one bucket with `lanes` lanes per arc: every member's arcs in
@@ -298,55 +305,90 @@ hipError_t enqueue_batch_arcs(pdr_batch *b, hipStream_t st)
     return hipSuccess;
 }
 
-// `count` batched passes: each group's height launch (objective and stop test
-// included) and arc launches on a stream of its own (group 0 on st, group g on
-// aux[g]), forked from st at the start and joined back at the end.
-hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st, hipStream_t *aux)
+// One batched pass of group g on sg: its height launch (objective and stop test
+// included), then its buckets' arc launches.
+hipError_t enqueue_group_pass(pdr_batch *b, int g, hipStream_t sg)
 {
     const bool fp64 = b->precision == PDR_FP64;
+    const auto &grp = b->groups[g];
+    hipError_t e = pdr::launch_bheight(group_views(b, g), grp.cnt, grp.d_hmap, grp.nhblocks, fp64,
+                                       b->height_unroll, sg);
+    for (size_t k = 0; k < b->buckets.size() && e == hipSuccess; ++k) {
+        const auto &bk = b->buckets[k];
+        if (bk.group == g)
+            e = pdr::launch_barc(b->method, group_views(b, g), bk.d_amap, bk.nblocks, fp64, bk.tl,
+                                 sg);
+    }
+    return e;
+}
+
+// The group streams (group 0 on st, group g on aux[g]) wait for st...
+hipError_t fork_groups(pdr_batch *b, hipStream_t st, hipStream_t *aux)
+{
     const int G = (int)b->groups.size();
     hipError_t e = hipSuccess;
     if (G > 1) e = hipEventRecord(b->fork, st);
     for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(aux[g], b->fork, 0);
-    for (int64_t q = 0; q < count && e == hipSuccess; ++q)
-        for (int g = 0; g < G && e == hipSuccess; ++g) {
-            hipStream_t sg = g == 0 ? st : aux[g];
-            const auto &grp = b->groups[g];
-            e = pdr::launch_bheight(group_views(b, g), grp.cnt, grp.d_hmap, grp.nhblocks, fp64,
-                                    b->height_unroll, sg);
-            for (size_t k = 0; k < b->buckets.size() && e == hipSuccess; ++k) {
-                const auto &bk = b->buckets[k];
-                if (bk.group == g)
-                    e = pdr::launch_barc(b->method, group_views(b, g), bk.d_amap, bk.nblocks,
-                                         fp64, bk.tl, sg);
-            }
-        }
-    for (int g = 1; g < G && e == hipSuccess; ++g) {
+    return e;
+}
+
+// ... and st waits for them.
+hipError_t join_groups(pdr_batch *b, hipStream_t st, hipStream_t *aux)
+{
+    hipError_t e = hipSuccess;
+    for (int g = 1; g < (int)b->groups.size() && e == hipSuccess; ++g) {
         e = hipEventRecord(b->join[g], aux[g]);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[g], 0);
     }
     return e;
 }
 
-pdr_status batch_graph(pdr_batch *b, hipGraphExec_t *out)
+// `count` batched passes, each group's on a stream of its own, forked from st
+// at the start and joined back at the end.
+hipError_t enqueue_batch_passes(pdr_batch *b, int64_t count, hipStream_t st, hipStream_t *aux)
 {
-    if (!b->gexec) {
-        if (!b->cap_stream)
-            PDR_BCHECK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-        for (auto &x : b->cap_aux)
-            if (!x) PDR_BCHECK(b, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    const int G = (int)b->groups.size();
+    hipError_t e = fork_groups(b, st, aux);
+    for (int64_t q = 0; q < count && e == hipSuccess; ++q)
+        for (int g = 0; g < G && e == hipSuccess; ++g)
+            e = enqueue_group_pass(b, g, g == 0 ? st : aux[g]);
+    if (e == hipSuccess) e = join_groups(b, st, aux);
+    return e;
+}
+
+// Capture graph_sweeps passes of each group into a graph of its own.
+pdr_status batch_graphs(pdr_batch *b)
+{
+    if (b->have_graphs) return PDR_OK;
+    if (!b->cap_stream)
+        PDR_BCHECK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    for (int g = 0; g < (int)b->groups.size(); ++g) {
         PDR_BCHECK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_batch_passes(b, b->graph_sweeps, b->cap_stream, b->cap_aux);
+        hipError_t e = hipSuccess;
+        for (int64_t q = 0; q < b->graph_sweeps && e == hipSuccess; ++q)
+            e = enqueue_group_pass(b, g, b->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
-        PDR_BCHECK(b, e);
-        PDR_BCHECK(b, e2);
-        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        PDR_BCHECK(b, e);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[g], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            PDR_BCHECK(b, e);
+        }
     }
-    *out = b->gexec;
+    b->have_graphs = true;
     return PDR_OK;
+}
+
+// graph_sweeps passes: every group's graph on its own stream.
+hipError_t launch_batch_graphs(pdr_batch *b)
+{
+    hipError_t e = fork_groups(b, b->stream, b->aux);
+    for (int g = 0; g < (int)b->groups.size() && e == hipSuccess; ++g)
+        e = hipGraphLaunch(b->gexec[g], g == 0 ? b->stream : b->aux[g]);
+    if (e == hipSuccess) e = join_groups(b, b->stream, b->aux);
+    return e;
 }
 
 pdr_status count_stopped(pdr_batch *b, int32_t *n)
@@ -381,8 +423,6 @@ void batch_free(pdr_batch *b)
     b->d_views = nullptr;
     b->d_count = nullptr;
     b->h_count = nullptr;
-    for (auto &x : b->cap_aux)
-        if (x) (void)hipStreamDestroy(x);
     for (auto &x : b->aux)
         if (x) (void)hipStreamDestroy(x);
     for (auto &x : b->join)
@@ -573,15 +613,16 @@ static pdr_status pdr_batch_sweep_body(pdr_batch *b, int64_t max_sweeps, double 
     PDR_BCHECK(b, pdr::launch_bbegin(b->d_views, b->B, eps_obj, z_target, b->stream));
     const bool poll = eps_obj > 0.0 || z_target > 0.0;
     const int64_t G = b->graph_sweeps;
-    hipGraphExec_t ge = nullptr;
+    bool graphs = false;
     if (G > 0 && max_sweeps >= G) {
-        st = batch_graph(b, &ge);
+        st = batch_graphs(b);
         if (st != PDR_OK) return st;
+        graphs = true;
     }
     int64_t s = 0, since = 0, every = 16;
     while (s < max_sweeps) {
-        if (ge && max_sweeps - s >= G) {
-            PDR_BCHECK(b, hipGraphLaunch(ge, b->stream));
+        if (graphs && max_sweeps - s >= G) {
+            PDR_BCHECK(b, launch_batch_graphs(b));
             s += G;
             since += G;
         } else {
