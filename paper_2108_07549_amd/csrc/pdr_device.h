@@ -706,7 +706,14 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
     group_sum<L, 2>(red, lds, phase);
     double Ssum = red[0], P = red[1];
     double half = 0.0;  // psi/2 (ESO) or lambda (CAP): the shift of the active c
-    if (Ssum > u) {
+    // Without congestion the new row is max(0, c): its terms, and their
+    // summation order, are those of the reduction above, so its sum is Ssum
+    // exactly and the group (which ends with this arc) needs no second
+    // reduction.
+    const bool congested = Ssum > u;
+    if (!congested) {
+        if (lane == 0) Fsum[e] = Ssum;
+    } else {
         double theta = 0.0;
         for (;;) {
             half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
@@ -746,8 +753,10 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
             store_vec_s<NT>(fo + q * V, o);
         }
     }
-    group_sum<L, 1>(fs, lds, phase);
-    if (lane == 0) Fsum[e] = fs[0];
+    if (congested) {
+        group_sum<L, 1>(fs, lds, phase);
+        if (lane == 0) Fsum[e] = fs[0];
+    }
 }
 
 template <typename T, int L, int NV, bool CAP, bool NT>
