@@ -679,19 +679,28 @@ __device__ __forceinline__ void eso_arc(const DevGraph &g, T *__restrict__ f, co
     const T *hj = h + (int64_t)g.heads[e] * Kp;
     const double u = g.u[e];
 
+    // The lane's f vectors are all requested before the first is used, so the
+    // whole row is in flight at once (a lane past the row's end re-reads its
+    // last vector, which stays in bounds, and keeps c = 0); the h rows, mostly
+    // cache hits, follow one vector at a time.
     T c[NV][V];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int q = v * L + lane;
+        load_vec_s<NT>(fe + (q < nvec ? q : nvec - 1) * V, c[v]);
+    }
     double red[2] = {0.0, 0.0};
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int q = v * L + lane;
         if (q < nvec) {
-            T a[V], b[V], x[V];
-            load_vec_s<NT>(fe + q * V, x);
+            T a[V], b[V];
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, b);
 #pragma unroll
             for (int w = 0; w < V; ++w) {
-                const T cc = (T)0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
+                const T x = c[v][w];
+                const T cc = (T)0.5 * ((a[w] + x) - (b[w] - x));
                 c[v][w] = cc;
                 if (cc > (T)0) {
                     red[0] += (double)cc;
