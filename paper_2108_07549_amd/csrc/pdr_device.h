@@ -1087,30 +1087,32 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_rowsum(DevGraph g, const T 
 
 // ----------------------------------------------------------------- long rows
 // Rows longer than the register-resident arc kernels hold (more than
-// kStreamMinVectors 16-byte vectors): one block of kStreamLanes lanes per
-// arc streams the row in tiles of kStreamLanes x TV vectors and recomputes
-// the row's values from f, h_i and h_j on every pass over it, with the same
+// max_tiling_vectors() 16-byte vectors): one block of kStreamLanes lanes per
+// arc streams the row in tiles of kStreamLanes x TV vectors, with the same
 // per-element arithmetic as the resident kernels. PDR-ESO needs one pass
-// (reading f, h_i, h_j and writing f) for an arc within capacity, and for a
-// congested one also a pass over its own row per step of the threshold
-// iteration and one for the update; PDR-AGD and PDR-GDM one pass for their
-// sums and one for the update (if accepted). Stores are streaming.
+// (reading f, h_i, h_j and writing max(0, c) in place) for an arc within
+// capacity, and for a congested one also a pass over its own row per step of
+// the threshold iteration and one for the update; PDR-AGD and PDR-GDM one
+// pass that stores the stepped row in place (and a second that restores it
+// if the step is rejected). Stores are streaming.
 constexpr int kStreamLanes = 1024;
 // vectors per lane of one tile; Tiling{kStreamLanes, -kStreamTile} names the
 // streamed arc kernels
 constexpr int kStreamTile = 4;
 
-template <typename T>
-__device__ __forceinline__ void stream_c(const T *__restrict__ fe, const T *__restrict__ hi,
-                                         const T *__restrict__ hj, int q, T (&c)[VecT<T>::N])
+// The TV vectors of lane `lane` in the tile at `base` of a streamed row, all
+// requested before any is used (a lane past the row's end re-reads its last
+// vector, which stays in bounds; callers skip it).
+template <typename T, int TV>
+__device__ __forceinline__ void load_tile(const T *__restrict__ p, int base, int lane, int nvec,
+                                          T (&x)[TV][VecT<T>::N])
 {
     constexpr int V = VecT<T>::N;
-    T a[V], b[V], x[V];
-    load_vec(fe + q * V, x);
-    load_vec(hi + q * V, a);
-    load_vec(hj + q * V, b);
 #pragma unroll
-    for (int w = 0; w < V; ++w) c[w] = (T)0.5 * ((a[w] + x[w]) - (b[w] - x[w]));
+    for (int v = 0; v < TV; ++v) {
+        const int q = base + v * kStreamLanes + lane;
+        load_vec(p + (q < nvec ? q : nvec - 1) * V, x[v]);
+    }
 }
 
 // The first pass also stores max(c, 0) in place of the row. Every later step
@@ -1134,24 +1136,29 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
     const T *hj = h + (int64_t)g.heads[e] * Kp;
     const double u = g.u[e];
     double red[2] = {0.0, 0.0};
-    for (int base = 0; base < nvec; base += L * TV)
+    for (int base = 0; base < nvec; base += L * TV) {
+        T x[TV][V];
+        load_tile<T, TV>(fe, base, lane, nvec, x);
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T c[V], o[V];
-                stream_c(fe, hi, hj, q, c);
+                T a[V], b[V], o[V];
+                load_vec(hi + q * V, a);
+                load_vec(hj + q * V, b);
 #pragma unroll
                 for (int w = 0; w < V; ++w) {
-                    o[w] = c[w] > (T)0 ? c[w] : (T)0;
-                    if (c[w] > (T)0) {
-                        red[0] += (double)c[w];
+                    const T c = (T)0.5 * ((a[w] + x[v][w]) - (b[w] - x[v][w]));
+                    o[w] = c > (T)0 ? c : (T)0;
+                    if (c > (T)0) {
+                        red[0] += (double)c;
                         red[1] += 1.0;
                     }
                 }
                 store_vec_s<true>(fe + q * V, o);
             }
         }
+    }
     group_sum<L, 2>(red, lds, phase);
     double Ssum = red[0], P = red[1];
     if (Ssum <= u) {
@@ -1166,16 +1173,16 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
         half = CAP ? (Ssum - u) / P : 0.5 * ((Ssum - u) / (1.0 + 0.5 * P));
         const double th = fmax(theta, half);
         double r2[2] = {0.0, 0.0};
-        for (int base = 0; base < nvec; base += L * TV)
+        for (int base = 0; base < nvec; base += L * TV) {
+            T x[TV][V];
+            load_tile<T, TV>(fe, base, lane, nvec, x);
 #pragma unroll
             for (int v = 0; v < TV; ++v) {
                 const int q = base + v * L + lane;
                 if (q < nvec) {
-                    T x[V];
-                    load_vec(fe + q * V, x);
 #pragma unroll
                     for (int w = 0; w < V; ++w) {
-                        const double cc = (double)x[w];
+                        const double cc = (double)x[v][w];
                         if (cc > th) {
                             r2[0] += cc;
                             r2[1] += 1.0;
@@ -1183,6 +1190,7 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
                     }
                 }
             }
+        }
         group_sum<L, 2>(r2, lds, phase);
         if (r2[1] == P || (CAP && r2[1] == 0.0)) break;
         Ssum = r2[0];
@@ -1190,22 +1198,24 @@ __device__ __forceinline__ void eso_arc_stream(const DevGraph &g, T *__restrict_
         theta = th;
     }
     double fs[1] = {0.0};
-    for (int base = 0; base < nvec; base += L * TV)
+    for (int base = 0; base < nvec; base += L * TV) {
+        T x[TV][V];
+        load_tile<T, TV>(fe, base, lane, nvec, x);
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T x[V], o[V];
-                load_vec(fe + q * V, x);
+                T o[V];
 #pragma unroll
                 for (int w = 0; w < V; ++w) {
-                    const double val = (double)x[w] - half;
+                    const double val = (double)x[v][w] - half;
                     o[w] = (T)(val > 0.0 ? val : 0.0);
                     fs[0] += (double)o[w];
                 }
                 store_vec_s<true>(fe + q * V, o);
             }
         }
+    }
     group_sum<L, 1>(fs, lds, phase);
     if (lane == 0) Fsum[e] = fs[0];
 }
@@ -1251,24 +1261,25 @@ __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict_
     const double b = beta[e];
     const double gam = prm.gamma;
     double red[3] = {0.0, 0.0, 0.0};  // sum df, sum df (df - g), sum of the new values
-    for (int base = 0; base < nvec; base += L * TV)
+    for (int base = 0; base < nvec; base += L * TV) {
+        T x[TV][V], w0[TV][V];
+        load_tile<T, TV>(fe, base, lane, nvec, x);
+        if constexpr (GDM) load_tile<T, TV>(ve, base, lane, nvec, w0);
 #pragma unroll
         for (int v = 0; v < TV; ++v) {
             const int q = base + v * L + lane;
             if (q < nvec) {
-                T a[V], bb[V], x[V], w0[V], nf[V], nv[V];
-                load_vec(fe + q * V, x);
-                if constexpr (GDM) load_vec(ve + q * V, w0);
+                T a[V], bb[V], nf[V], nv[V];
                 load_vec(hi + q * V, a);
                 load_vec(hj + q * V, bb);
 #pragma unroll
                 for (int w = 0; w < V; ++w) {
                     const double gg = (double)(a[w] - bb[w]);
-                    const double fx = (double)x[w];
+                    const double fx = (double)x[v][w];
                     const double st = b * (gg - psi);
                     const double df = st > -fx ? st : -fx;
                     if constexpr (GDM) {
-                        const double vn = gam * (double)w0[w] + df;
+                        const double vn = gam * (double)w0[v][w] + df;
                         const double fn = fx + vn;
                         nv[w] = (T)vn;
                         nf[w] = (T)(fn > 0.0 ? fn : 0.0);
@@ -1279,14 +1290,15 @@ __device__ __forceinline__ void agd_arc_stream(const DevGraph &g, T *__restrict_
                     red[1] += df * (df - gg);
                     red[2] += (double)nf[w];
                 }
-                store_vec_s<true>(uf + q * V, x);
+                store_vec_s<true>(uf + q * V, x[v]);
                 store_vec_s<true>(fe + q * V, nf);
                 if constexpr (GDM) {
-                    store_vec_s<true>(uv + q * V, w0);
+                    store_vec_s<true>(uv + q * V, w0[v]);
                     store_vec_s<true>(ve + q * V, nv);
                 }
             }
         }
+    }
     group_sum<L, 3>(red, lds, phase);
     const double before = F - u, after = F + red[0] - u;
     const double dcong = (before > 0.0 && after > 0.0)
