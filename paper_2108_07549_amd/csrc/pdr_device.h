@@ -827,7 +827,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void kb_eso(const InstView *__rest
 // dz = 1/2[(F + sum df - u)_+^2 - psi^2] + sum_k df_k (df_k - (h_ik - h_jk)),
 // is <= 0; otherwise beta <- max(beta_min, alpha_dec beta). Every inc_period
 // iterations beta <- min(beta_max, alpha_inc beta).
-template <typename T, int L, int NV, bool NT = true>
+template <typename T, int L, int NV, bool NT = true, bool RowFirst = false>
 __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, const T *__restrict__ h, double *__restrict__ Fsum, double *__restrict__ beta, const AgdParams &prm, const Ctrl *__restrict__ ctrl, int64_t slot, int lane, double *lds)
 {
     constexpr int V = VecT<T>::N;
@@ -843,20 +843,34 @@ __device__ __forceinline__ void agd_arc(const DevGraph &g, T *__restrict__ f, co
     const double psi = F > u ? F - u : 0.0;
     const double b = beta[e];
 
-    T cand[NV][V];  // the stepped row f + df, written only if the step is accepted
+    // the stepped row f + df, written only if the step is accepted; it first
+    // holds the row itself. RowFirst: all of a lane's f vectors are requested
+    // before the first is used (a lane past the row's end re-reads its last
+    // vector); otherwise they are loaded one vector at a time, which needs
+    // fewer registers. The single-instance AGD kernel takes RowFirst with 512
+    // or more lanes per arc, where it leaves the occupancy unchanged.
+    constexpr bool kRowFirst = RowFirst;
+    T cand[NV][V];
+    if constexpr (kRowFirst) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int q = v * L + lane;
+            load_vec_s<NT>(fe + (q < nvec ? q : nvec - 1) * V, cand[v]);
+        }
+    }
     double red[3] = {0.0, 0.0, 0.0};  // sum df, sum df (df - g), sum of stepped values
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int q = v * L + lane;
         if (q < nvec) {
-            T a[V], bb[V], x[V];
-            load_vec_s<NT>(fe + q * V, x);
+            T a[V], bb[V];
+            if constexpr (!kRowFirst) load_vec_s<NT>(fe + q * V, cand[v]);
             load_vec(hi + q * V, a);
             load_vec(hj + q * V, bb);
 #pragma unroll
             for (int w = 0; w < V; ++w) {
                 const double gg = (double)(a[w] - bb[w]);
-                const double fx = (double)x[w];
+                const double fx = (double)cand[v][w];
                 const double step = b * (gg - psi);
                 const double df = step > -fx ? step : -fx;
                 cand[v][w] = (T)(fx + df);
@@ -914,7 +928,7 @@ __global__ __launch_bounds__(ArcShape<L>::BS) void k_agd(DevGraph g, T *__restri
     const int lane = (L >= S::BS) ? (int)threadIdx.x : (int)threadIdx.x & (L - 1);
     const int64_t slot = blk * S::GPB + grp;
     if (L <= 64 && slot >= g.m) return;
-    agd_arc<T, L, NV, NT>(g, f, h, Fsum, beta, prm, ctrl, slot, lane, lds);
+    agd_arc<T, L, NV, NT, (L >= 512)>(g, f, h, Fsum, beta, prm, ctrl, slot, lane, lds);
 }
 
 // Batched: amap[logical block] = (instance, block within the instance's arcs).
