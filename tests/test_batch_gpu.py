@@ -6,6 +6,7 @@ instance bit for bit (the objective's partial sums are grouped differently, so
 z agrees to rounding). Members are also checked against the FP64 oracle, for
 per-instance stopping, graph replays and the autotuner.
 """
+import functools
 import sys
 
 import numpy as np
@@ -226,28 +227,85 @@ def test_batch_rejects_a_bad_instance():
     assert ei.value.status == 1 and "instance 1" in ei.value.message
 
 
+@functools.lru_cache(maxsize=1)
+def bench_batch():
+    """The benchmark's 256-instance batch (seed 4), generated once per module."""
+    from gen.batch import recipe_batch
+    return tuple(recipe_batch(256, 4))
+
+
+def sampled_members(insts, extra=5, seed=7):
+    """Members of the benchmark batch checked against the oracle: the largest,
+    smallest and median by work (m K), the most overloaded certified-infeasible
+    member, and `extra` more drawn with a fixed seed."""
+    work = np.array([i.m * i.K for i in insts])
+    order = np.argsort(work, kind="stable")
+    picks = [int(order[-1]), int(order[0]), int(order[len(order) // 2])]
+    infeasible = [q for q, i in enumerate(insts) if i.meta.get("certified") == "infeasible"]
+    assert infeasible
+    worst = max(infeasible, key=lambda q: insts[q].meta["load_factor"])
+    if worst not in picks:
+        picks.append(worst)
+    rest = [q for q in range(len(insts)) if q not in picks]
+    picks += [int(q) for q in np.random.default_rng(seed).choice(rest, extra, replace=False)]
+    return picks
+
+
 @pytest.mark.parametrize("method", list(METHODS))
 def test_full_batch_sampled_members_match_the_oracle(method):
     """The 256-instance batch the benchmark times (FP64; tuned for ESO, the
-    benchmark's method): the largest, smallest and median members after 3
-    sweeps against the oracle."""
-    from gen.batch import recipe_batch
+    benchmark's method): sampled members (largest, smallest, median, the most
+    overloaded certified-infeasible one and five more) after 3 sweeps against
+    the oracle."""
     gm, om = METHODS[method]
-    insts = recipe_batch(256, 4)
-    work = np.array([i.m * i.K for i in insts])
-    order = np.argsort(work)
-    picks = [int(order[-1]), int(order[0]), int(order[len(order) // 2])]
+    insts = list(bench_batch())
+    picks = sampled_members(insts)
     with pdr.Batch(insts, method=gm, precision=pdr.FP64) as b:
         if method == "eso":
             say("full batch buckets", b.tune(reps=2))
         b.sweep(3)
         for q in picks:
             inst = insts[q]
-            say("full batch member", method, q, inst.n, inst.m, inst.K)
+            say("full batch member", method, q, inst.n, inst.m, inst.K, inst.meta.get("certified"))
             st, zo = oracle.run(inst, om, 3)
             c = b.member(q)
             assert np.max(np.abs(c.flows() - st.f)) <= flow_tol(inst), q
             assert np.allclose(c.z_log(0, 3), zo, rtol=1e-11, atol=0), q
+
+
+# FP32 bulk against the FP64 oracle: T passes round each stored flow and height
+# once per pass (u32 = 2^-24), so with no error of the pass map's own they stay
+# within T * u32 * max(u) (flow units) and z within T * u32 relative; the
+# single-instance tests state the same bounds.
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("method", ["eso", "agd", "gdm"])
+def test_full_batch_fp32_sampled_members_within_the_fp32_bound(method):
+    """The benchmark batch in FP32 bulk storage, 32 passes (one captured graph
+    per member group): sampled members' flows, heights and z trajectories
+    against the FP64 oracle of the same passes, within the stated FP32
+    bounds."""
+    gm, om = METHODS[method]
+    T = 32
+    insts = list(bench_batch())
+    picks = sampled_members(insts)
+    with pdr.Batch(insts, method=gm, precision=pdr.FP32_BULK) as b:
+        b.sweep(T)
+        for q in picks:
+            inst = insts[q]
+            st, zo = oracle.run(inst, om, T)
+            _, ho = oracle.excess(inst, st.f)
+            c = b.member(q)
+            umax = float(np.max(inst.u))
+            err = dict(flow=float(np.max(np.abs(c.flows() - st.f))),
+                       height=float(np.max(np.abs(c.heights() - ho))),
+                       z_rel=float(np.max(np.abs(c.z_log(0, T) - zo) / np.abs(zo))))
+            say("fp32 batch member", method, q, inst.n, inst.K, inst.meta.get("certified"), err,
+                "bound", T * U32 * umax)
+            assert err["flow"] <= T * U32 * umax, (q, err)
+            assert err["height"] <= T * U32 * umax, (q, err)
+            assert err["z_rel"] <= T * U32, (q, err)
 
 
 # Certified members of the benchmark batch that reach a decided verdict within
@@ -262,8 +320,7 @@ def test_certified_members_reach_their_certified_verdict():
     infeasible, a proof by weak duality; z <= 1e-8: feasible) or a pass cap.
     Every decided verdict equals the member's certified label (Theorems 1-2)
     and the oracle's verdict of the same iterate."""
-    from gen.batch import recipe_batch
-    insts = recipe_batch(256, 4)
+    insts = list(bench_batch())
     sub = [insts[q] for q in VERDICT_MEMBERS]
     labels = [i.meta["certified"] for i in sub]
     assert labels.count("feasible") == 4 and labels.count("infeasible") == 2
