@@ -167,90 +167,6 @@ def congestion_bracket(inst, gap: float = 1e-3, max_iter: int = 80, verbose: boo
                 seconds=time.time() - t0)
 
 
-def _all_or_nothing(n, tails, heads, lengths, s, t, d, chunk=256):
-    """Arc loads of routing every commodity on one shortest path under `lengths`,
-    and the shortest-path distances. Loads are accumulated on each source's
-    shortest-path tree (subtree demand sums, leaves first)."""
-    m = len(heads)
-    A = csr_matrix((lengths, (tails, heads)), shape=(n, n))
-    keys = tails.astype(np.int64) * n + heads.astype(np.int64)
-    order = np.argsort(keys, kind="stable")
-    skeys = keys[order]
-    load = np.zeros(m)
-    dist = np.empty(len(s))
-    srcs, inv = np.unique(s, return_inverse=True)
-    for c0 in range(0, len(srcs), chunk):
-        block = srcs[c0:c0 + chunk]
-        D, P = dijkstra(A, directed=True, indices=block, return_predecessors=True)
-        ks = np.nonzero((inv >= c0) & (inv < c0 + len(block)))[0]
-        rows = inv[ks] - c0
-        dist[ks] = D[rows, t[ks]]
-        sink = np.zeros((len(block), n))
-        np.add.at(sink, (rows, t[ks]), d[ks])
-        for r in range(len(block)):
-            pred = P[r]
-            reach = np.nonzero(pred >= 0)[0]
-            if reach.size == 0:
-                continue
-            vs = reach[np.argsort(-D[r, reach], kind="stable")]  # leaves first
-            acc = sink[r].copy()
-            pv = pred[vs]
-            for v, p in zip(vs.tolist(), pv.tolist()):
-                acc[p] += acc[v]
-            arc = order[np.searchsorted(skeys, pv.astype(np.int64) * n + vs)]
-            np.add.at(load, arc, acc[vs])
-    return load, dist
-
-
-def congestion_bracket_fw(inst, iters: int = 60, kappa: float = 40.0, verbose: bool = False,
-                          time_limit: float = 3600.0):
-    """Min-congestion bracket by Frank-Wolfe on a softmax of arc congestion.
-
-    The routing is the running convex combination of all-or-nothing routings
-    (each a valid routing of all demands), so mu_hi = max_e load_e / u_e is the
-    congestion of an explicit routing. The softmax weights w give arc lengths
-    l = w / u and the weak-duality bound mu_lo = sum_k d_k dist_l / sum_e u_e l_e.
-    No LP is solved, so the cost per iteration is one shortest-path tree per
-    distinct source.
-    """
-    n, m = inst.n, inst.m
-    tails = inst.tails().astype(np.int64)
-    heads = inst.col.astype(np.int64)
-    u = inst.u.astype(np.float64)
-    d = inst.d.astype(np.float64)
-    s = inst.s.astype(np.int64)
-    t = inst.t.astype(np.int64)
-    t0 = time.time()
-    load, _ = _all_or_nothing(n, tails, heads, 1.0 / u, s, t, d)
-    mu_hi = float(np.max(load / u))
-    mu_lo = 0.0
-    it = 0
-    for it in range(1, iters + 1):
-        rho = load / u
-        mu = float(np.max(rho))
-        w = np.exp(kappa * (rho / mu - 1.0))
-        lens = w / u + 1e-12 / u
-        y, dist = _all_or_nothing(n, tails, heads, lens, s, t, d)
-        mu_lo = max(mu_lo, float(np.dot(d, dist) / np.dot(u, lens)))
-        # exact line search on the max congestion along the segment (piecewise
-        # linear in the step): sample finely, then keep the best point
-        best_g, best_val = 0.0, mu
-        for g in np.linspace(0.0, 1.0, 201)[1:]:
-            val = float(np.max(((1 - g) * load + g * y) / u))
-            if val < best_val:
-                best_g, best_val = float(g), val
-        if best_g == 0.0:
-            best_g = 2.0 / (it + 2.0)
-        load = (1 - best_g) * load + best_g * y
-        mu_hi = min(mu_hi, float(np.max(load / u)))
-        if verbose:
-            print(f"[fw] it {it} mu_hi {mu_hi:.6g} mu_lo {mu_lo:.6g} gap {mu_hi / mu_lo - 1:.3e} "
-                  f"step {best_g:.3f} t {time.time() - t0:.1f}s", flush=True)
-        if time.time() - t0 > time_limit:
-            break
-    return dict(mu_hi=mu_hi, mu_lo=mu_lo, iters=it, columns=0, seconds=time.time() - t0)
-
-
 def grid_cut_bound(inst, a: int, b: int) -> float:
     """Lower bound on the minimum congestion of an a x b grid instance from its
     straight cuts: every vertical or horizontal line splits the grid, and all
