@@ -268,6 +268,55 @@ def test_agd_objective_change_is_exact_subproblem_difference():
             assert b == max(1.0 / K, float(beta) / 2)
 
 
+def test_gdm_step_is_exact_algorithm_4_step():
+    """One GDM arc step of the oracle against Algorithm 4's step in exact
+    rationals: the gradient step and its objective change are Algorithm 3's
+    (Expression 13, optimal slack); an accepted step sets v' = gamma v + df and
+    f' = max(0, f + v') (so momentum can carry a flow past its own step, down
+    to zero), a rejected one keeps f and v and scales beta by alpha_dec
+    (floored at beta_min), and every inc_period-th pass scales beta by
+    alpha_inc (capped at beta_max). Dyadic inputs and gamma = 3/4 keep every
+    binary64 operation exact; both decisions and both t cases occur."""
+    rng = random.Random(44)
+    seen = set()
+    for _ in range(400):
+        K = rng.randint(1, 6)
+        hi = [Fr(rng.randint(-24, 24), 4) for _ in range(K)]
+        hj = [Fr(rng.randint(-24, 24), 4) for _ in range(K)]
+        fe = [Fr(rng.randint(0, 16), 2) for _ in range(K)]
+        ve = [Fr(rng.randint(-16, 16), 4) for _ in range(K)]
+        u = Fr(rng.randint(0, 40), 2)
+        beta = Fr(1, 2 ** rng.randint(1, 5))
+        t = rng.choice([3, 10, 20, 7])
+        prm = dict(beta_init=0.1, beta_min=1.0 / 16, beta_max=0.25, alpha_inc=2.0,
+                   alpha_dec=0.5, inc_period=10, gamma=0.75)
+        F = sum(fe, Fr(0))
+        psi = max(Fr(0), F - u)
+        dfs = [max(-fe[k], beta * (hi[k] - hj[k] - psi)) for k in range(K)]
+        dz = edge_objective(F, dfs, hi, hj, u) - edge_objective(F, [Fr(0)] * K, hi, hj, u)
+        acc_x = dz <= 0
+        if acc_x:
+            v_x = [Fr(3, 4) * ve[k] + dfs[k] for k in range(K)]
+            f_x = [max(Fr(0), fe[k] + v_x[k]) for k in range(K)]
+            b_x = beta
+        else:
+            v_x, f_x = list(ve), list(fe)
+            b_x = max(Fr(1, 16), beta / 2)
+        if t % 10 == 0:
+            b_x = min(Fr(1, 4), b_x * 2)
+        fo, vo, b, acc, dzo = oracle.gdm_edge([float(x) for x in hi], [float(x) for x in hj],
+                                              [float(x) for x in fe], [float(x) for x in ve],
+                                              float(u), t, float(beta), prm)
+        assert acc == acc_x
+        assert dzo == float(dz)
+        assert list(fo) == [float(x) for x in f_x]
+        assert list(vo) == [float(x) for x in v_x]
+        assert b == float(b_x)
+        seen.add((acc_x, t % 10 == 0, any(fe[k] + v_x[k] < 0 for k in range(K)) if acc_x else None))
+    assert {(True, True), (True, False), (False, True), (False, False)} <= {x[:2] for x in seen}
+    assert (True, False, True) in seen or (True, True, True) in seen  # momentum clipped at zero
+
+
 def test_agd_accept_decision_near_convergence():
     """Reading 12's factored congestion term, pinned where it decides: the two
     golden cases (tests/golden/agd_accept.txt) make the accept test of
