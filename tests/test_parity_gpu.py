@@ -389,6 +389,55 @@ def test_non_finite_objective_stops_and_is_reported(method):
             assert ei.value.status == 5
 
 
+def _golden_accept_rows():
+    import os
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "agd_accept.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                q = [x.strip() for x in line.split("|")]
+                rows[q[0]] = (float.fromhex(q[1]), float.fromhex(q[2]), float.fromhex(q[3]), q[4])
+    return rows
+
+
+@pytest.mark.parametrize("method", ["agd", "gdm"])
+@pytest.mark.parametrize("case", ["reject", "accept"])
+def test_accept_decision_where_a_difference_of_squares_would_flip_it(method, case):
+    """The accept test of Algorithms 3 and 4 on the GPU at the golden cases
+    (tests/golden/agd_accept.txt) where the objective change is a small
+    difference of large terms: a two-vertex instance (arcs 0->1 and 1->0, one
+    commodity 0 -> 1, u = 8) is put in the state f = (f_golden, 0), beta =
+    beta_golden, with d = f_golden + h_golden so that the arc's height
+    difference is the golden h_i exactly. One pass must take the exact
+    decision (the oracle's, pinned against rationals), with flows and learning
+    rates equal to the oracle's bit for bit."""
+    hi, f0, beta, decision = _golden_accept_rows()[case]
+    assert beta / 2 >= 1.0 / 64
+    d = f0 + hi
+    assert d - f0 == hi  # the height difference is exact
+    inst = make_instance(2, [(0, 1), (1, 0)], 8.0, [0], [1], [d])
+    gm, om = METHODS[method]
+    f = np.array([[f0], [0.0]])
+    b = np.array([beta, beta])
+    # beta_min below the default 1/K = 1, so that a rejection shows in beta
+    with ctx_for(inst, gm, agd={"beta_min": 1.0 / 64}) as c:
+        c.set_state(f, b, t=1, z_prev=math.inf, v=np.zeros((2, 1)) if gm == pdr.GDM else None)
+        c.sweep(1)
+        fg, bg = c.flows(), c.learning_rates()
+    st = oracle.State(inst, om, params=dict(oracle.default_params(om, 1), beta_min=1.0 / 64))
+    st.f[:] = f
+    st.beta[:] = b
+    st.t = 1
+    st.run(1)
+    say("accept decision", method, case, "f", fg[:, 0].tolist(), "beta", bg.tolist())
+    assert np.array_equal(fg, st.f) and np.array_equal(bg, st.beta)
+    if decision == "reject":
+        assert fg[0, 0] == f0 and bg[0] == beta / 2
+    else:
+        assert fg[0, 0] != f0 and bg[0] == beta
+
+
 @pytest.mark.parametrize("method", ALL)
 def test_degenerate_instances(method):
     gm, om = METHODS[method]
