@@ -401,36 +401,55 @@ def _golden_accept_rows():
     return rows
 
 
+@pytest.mark.parametrize("path", ["resident", "streamed", "batch"])
 @pytest.mark.parametrize("method", ["agd", "gdm"])
 @pytest.mark.parametrize("case", ["reject", "accept"])
-def test_accept_decision_where_a_difference_of_squares_would_flip_it(method, case):
+def test_accept_decision_where_a_difference_of_squares_would_flip_it(case, method, path):
     """The accept test of Algorithms 3 and 4 on the GPU at the golden cases
     (tests/golden/agd_accept.txt) where the objective change is a small
-    difference of large terms: a two-vertex instance (arcs 0->1 and 1->0, one
-    commodity 0 -> 1, u = 8) is put in the state f = (f_golden, 0), beta =
-    beta_golden, with d = f_golden + h_golden so that the arc's height
-    difference is the golden h_i exactly. One pass must take the exact
+    difference of large terms: a two-vertex instance (arcs 0->1 and 1->0,
+    commodity 0 from vertex 0 to 1, u = 8) is put in the state f = (f_golden,
+    0), beta = beta_golden, with d = f_golden + h_golden so that the arc's
+    height difference is the golden h_i exactly. One pass must take the exact
     decision (the oracle's, pinned against rationals), with flows and learning
-    rates equal to the oracle's bit for bit."""
+    rates equal to the oracle's bit for bit. Paths: the register-resident arc
+    kernel; the streamed long-row kernel (16,384 more commodities of zero
+    demand, which add nothing to the step or its objective change); a batch
+    member (the batched kernels, beside a second member)."""
     hi, f0, beta, decision = _golden_accept_rows()[case]
     assert beta / 2 >= 1.0 / 64
     d = f0 + hi
     assert d - f0 == hi  # the height difference is exact
-    inst = make_instance(2, [(0, 1), (1, 0)], 8.0, [0], [1], [d])
+    K = 16385 if path == "streamed" else 1
+    dd = np.zeros(K)
+    dd[0] = d
+    inst = make_instance(2, [(0, 1), (1, 0)], 8.0, [0] * K, [1] * K, dd)
     gm, om = METHODS[method]
-    f = np.array([[f0], [0.0]])
+    f = np.zeros((2, K))
+    f[0, 0] = f0
     b = np.array([beta, beta])
-    # beta_min below the default 1/K = 1, so that a rejection shows in beta
-    with ctx_for(inst, gm, agd={"beta_min": 1.0 / 64}) as c:
-        c.set_state(f, b, t=1, z_prev=math.inf, v=np.zeros((2, 1)) if gm == pdr.GDM else None)
-        c.sweep(1)
-        fg, bg = c.flows(), c.learning_rates()
-    st = oracle.State(inst, om, params=dict(oracle.default_params(om, 1), beta_min=1.0 / 64))
+    v = np.zeros((2, K)) if gm == pdr.GDM else None
+    # beta_min below the default 1/K, so that a rejection shows in beta
+    agd = {"beta_min": 1.0 / 64}
+    if path == "batch":
+        with pdr.Batch([inst, recipe_grid4_k8()], method=gm, precision=pdr.FP64, agd=agd) as bt:
+            c = bt.member(0)
+            c.set_state(f, b, t=1, z_prev=math.inf, v=v)
+            bt.sweep(1)
+            fg, bg = c.flows(), c.learning_rates()
+    else:
+        with ctx_for(inst, gm, agd=agd) as c:
+            if path == "streamed":
+                assert c.tiling()[1] < 0  # the row is streamed
+            c.set_state(f, b, t=1, z_prev=math.inf, v=v)
+            c.sweep(1)
+            fg, bg = c.flows(), c.learning_rates()
+    st = oracle.State(inst, om, params=dict(oracle.default_params(om, K), beta_min=1.0 / 64))
     st.f[:] = f
     st.beta[:] = b
     st.t = 1
     st.run(1)
-    say("accept decision", method, case, "f", fg[:, 0].tolist(), "beta", bg.tolist())
+    say("accept decision", method, case, path, "f", fg[:, 0].tolist(), "beta", bg.tolist())
     assert np.array_equal(fg, st.f) and np.array_equal(bg, st.beta)
     if decision == "reject":
         assert fg[0, 0] == f0 and bg[0] == beta / 2
