@@ -105,3 +105,57 @@ def test_batch_recipe_shapes_and_labels():
         assert np.all(inst.s != inst.t)
         assert inst.u.min() >= 100 and inst.u.max() <= 1000
         assert connected(inst)
+
+
+def _edge_lp_min_congestion(inst):
+    """Minimum congestion mu* of the instance's demands from the arc-commodity
+    LP (min mu s.t. conservation of every commodity at every vertex,
+    sum_k f_ek <= mu u_e, f >= 0), solved directly with HiGHS: an independent
+    reference for the path column generation of gen.loadfactor."""
+    from scipy.optimize import linprog
+    from scipy.sparse import coo_matrix
+    n, m, K = inst.n, inst.m, inst.K
+    tails = inst.tails().astype(np.int64)
+    heads = inst.col.astype(np.int64)
+    e = np.repeat(np.arange(m), K)
+    k = np.tile(np.arange(K), m)
+    var = e * K + k
+    A_eq = coo_matrix((np.concatenate([np.ones(m * K), -np.ones(m * K)]),
+                       (np.concatenate([tails[e] * K + k, heads[e] * K + k]),
+                        np.concatenate([var, var]))), shape=(n * K, m * K + 1)).tocsr()
+    b_eq = np.zeros(n * K)
+    np.add.at(b_eq, inst.s.astype(np.int64) * K + np.arange(K), inst.d)
+    np.add.at(b_eq, inst.t.astype(np.int64) * K + np.arange(K), -inst.d)
+    A_ub = coo_matrix((np.concatenate([np.ones(m * K), -inst.u]),
+                       (np.concatenate([e, np.arange(m)]),
+                        np.concatenate([var, np.full(m, m * K)]))), shape=(m, m * K + 1)).tocsr()
+    c = np.zeros(m * K + 1)
+    c[-1] = 1.0
+    res = linprog(c, A_ub=A_ub, b_ub=np.zeros(m), A_eq=A_eq, b_eq=b_eq, bounds=(0, None),
+                  method="highs")
+    assert res.status == 0
+    return float(res.fun)
+
+
+def test_congestion_bracket_contains_the_lp_optimum():
+    """The certified bracket behind every load-factor scaling: on small
+    instances the column-generation bracket mu_lo <= mu* <= mu_hi
+    (gen.loadfactor) contains the minimum congestion of the arc-commodity LP
+    and closes to its gap; the straight-cut bound of a grid is below it; and a
+    demand scaling by LF / mu_hi (feasible label) or LF / mu_lo (infeasible
+    label) puts the LP's minimum congestion on the labelled side of 1."""
+    from gen.loadfactor import congestion_bracket, grid_cut_bound
+    cases = [recipe_small("knn", 50, 12, seed=3, u_range=(5, 20), d_range=(1, 9)),
+             recipe_small("knn", 80, 25, seed=4, u_range=(10, 40), d_range=(1, 20)),
+             recipe_small("grid", 5, 10, seed=5, u_range=(5, 20), d_range=(1, 9))]
+    for q, inst in enumerate(cases):
+        mu = _edge_lp_min_congestion(inst)
+        br = congestion_bracket(inst, gap=1e-6, max_iter=200)
+        assert br["mu_lo"] <= mu * (1 + 1e-7) and mu <= br["mu_hi"] * (1 + 1e-7), (q, br, mu)
+        assert br["mu_hi"] <= br["mu_lo"] * (1 + 1e-6), (q, br)
+        if q == 2:
+            assert grid_cut_bound(inst, 5, 5) <= mu * (1 + 1e-9)
+        for lf in (0.9, 1.05):
+            alpha = lf / (br["mu_hi"] if lf <= 1 else br["mu_lo"])
+            mus = _edge_lp_min_congestion(inst.demand_scaled(alpha))
+            assert (mus <= 1.0 + 1e-9) if lf <= 1 else (mus > 1.0), (q, lf, mus)
