@@ -239,3 +239,54 @@ def test_host_allocation_failure_is_a_status_not_an_exception():
     st, null_handle, msg = r.stdout.strip().split(" ", 2)
     assert int(st) == 2 and null_handle == "True"
     assert "host memory allocation failed" in msg
+
+
+C_CALLER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "pdr.h"
+
+int main(void)
+{
+    pdr_options o;
+    pdr_default_options(&o);
+    if (o.method != PDR_ESO || o.precision != PDR_FP64 || o.agd.beta_init != 0.25 ||
+        o.gdm.gamma != 0.9 || o.z_feasible_tol != 1e-8 || o.stream != NULL)
+        return 10;
+    /* a triangle 0 -> 1 -> 2 -> 0 with a self-loop 2 -> 2 appended: rejected
+       before any device call */
+    const int64_t row_ptr[4] = {0, 1, 2, 4};
+    const int32_t col[4] = {1, 2, 0, 2};
+    const double u[4] = {1, 1, 1, 1};
+    const int32_t s[1] = {0}, t[1] = {2};
+    const double d[1] = {1};
+    pdr_ctx *ctx = (pdr_ctx *)1;
+    pdr_status st = pdr_init(&ctx, 3, 4, row_ptr, col, u, 1, s, t, d, &o);
+    if (st != PDR_ERR_INVALID || ctx != NULL) return 11;
+    const char *msg = pdr_last_error(NULL);
+    if (msg == NULL || strstr(msg, "self-loop") == NULL) return 12;
+    if (pdr_sweep(NULL, 1, 0.0, 0.0) != PDR_ERR_INVALID) return 13;
+    pdr_destroy(NULL);
+    printf("ok\n");
+    return 0;
+}
+"""
+
+
+def test_header_is_plain_c_and_the_library_serves_a_c_caller(tmp_path):
+    """include/pdr.h compiles as strict C99 (-pedantic -Werror), and a C program
+    linked against libpdr.so gets the defaults of the paper's settings and the
+    documented argument errors, with no Python in between."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "caller.c"
+    src.write_text(C_CALLER)
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(pdr.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                           "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                           "-L", libdir, "-lpdr", "-Wl,-rpath," + libdir])
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.returncode, r.stderr[-2000:])
