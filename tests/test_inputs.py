@@ -159,3 +159,17 @@ def test_congestion_bracket_contains_the_lp_optimum():
             alpha = lf / (br["mu_hi"] if lf <= 1 else br["mu_lo"])
             mus = _edge_lp_min_congestion(inst.demand_scaled(alpha))
             assert (mus <= 1.0 + 1e-9) if lf <= 1 else (mus > 1.0), (q, lf, mus)
+
+
+def test_knn_neighbours_equal_brute_force():
+    """gen.graphs.knn_points: each point's 4 nearest neighbours (ties by index)
+    equal a brute-force search over all pairwise distances of the same points."""
+    from gen.graphs import knn_points
+    for seed in (1, 2, 3):
+        pts, nbrs = knn_points(300, np.random.default_rng(seed))
+        d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+        np.fill_diagonal(d2, np.inf)
+        idx = np.arange(len(pts))
+        for i in range(len(pts)):
+            want = np.lexsort((idx, d2[i]))[:4]
+            assert np.array_equal(nbrs[i], want), (seed, i)
